@@ -1,0 +1,189 @@
+"""Throughput of the fused stencil sweep on one MI355X, beside the plain sweep
+and the FP64 CPU oracle.
+
+Workload: 3D 7-point star (r = 1), 512^3 grid, FP32 storage and arithmetic,
+zero halo, T = 64 steps, seeded normalised weights and a U[-1, 1) field.
+One timed step = one whole sweep (stencil_run, T = 64, with the tuned fused
+depth k, tile variant and z-chunk) followed by the FP64 checksum reduction of
+u_T, inputs resident in HBM.  The plain one-step-per-launch sweep (k = 1) is
+timed the same way for the speedup.
+
+Prints one JSON line.  Usage:
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GStencil/s + % HBM roofline, fused vs plain sweep, 3D7P 512^3 FP32"
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_stream3d_7p_512.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("stream_kernel.hpp", "device_common.hpp", "variants.hpp", "launch.hpp"):
+        with open(os.path.join(ROOT, "paper_2103_08825_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def time_sweep(plan, x, y, T, steps, warmup, with_reduce=True):
+    """Returns (ms per step, ms of the sweeps alone per step) with HIP events on
+    torch's current stream, the stream the library launches on."""
+    import torch
+    from paper_2103_08825_amd import reduce
+    for _ in range(warmup):
+        plan.run(x, T, out=y)
+        if with_reduce:
+            reduce(y)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b, c in ev:
+        a.record()
+        plan.run(x, T, out=y)
+        b.record()
+        if with_reduce:
+            reduce(y)
+        c.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    total = sum(a.elapsed_time(c) for a, b, c in ev) / steps
+    sweep = sum(a.elapsed_time(b) for a, b, c in ev) / steps
+    return total, sweep, wall
+
+
+def cpu_baseline(u0_f64, coeffs, r, kind, bc, budget_s=12.0):
+    """The oracle as it stands, on the host cores, over a bounded number of steps
+    of the same grid."""
+    import oracle
+    threads = oracle.max_threads()
+    _, s1 = oracle.run(u0_f64, coeffs, 1, r=r, kind=kind, bc=bc, return_seconds=True)
+    steps = max(1, min(64, int(budget_s / max(s1, 1e-3))))
+    _, secs = oracle.run(u0_f64, coeffs, steps, r=r, kind=kind, bc=bc, return_seconds=True)
+    pts = u0_f64.size * steps
+    return {"value": pts / secs / 1e9, "unit": "GStencil/s", "cores": threads, "kind": "oracle",
+            "sample": "full %s grid, %d of the 64 steps (FP64 loop nest, OpenMP over the grid)"
+                      % ("x".join(str(s) for s in u0_f64.shape), steps),
+            "seconds": secs}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--T", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--fused-k", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print("bench.py measures one GPU: the sweep of one grid runs on one device; "
+              "--gpus %d is not supported (multi-GPU slab decomposition is design-only)" % a.gpus,
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2103_08825_amd import Plan, workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    n, T = a.n, a.T
+    case = W.case_3d("3d7p", seed=0, n=n, T=T)
+    log("inputs: %s %s T=%d" % (case.name, case.shape, T))
+    x = torch.from_numpy(case.u0).to(torch.float32).cuda()
+    y = torch.empty_like(x)
+
+    fused = Plan(case.shape, case.r, case.kind, case.coeffs, case.bc, "f32", method="fused",
+                 fused_k=a.fused_k, variant=a.variant, chunk=a.chunk)
+    if not a.no_autotune:
+        t0 = time.time()
+        fused.autotune()
+        log("autotune (fused) %.1fs -> %s" % (time.time() - t0, fused.info()))
+    info = fused.info()
+    k = info["fused_k"]
+    ms, ms_sweep, wall = time_sweep(fused, x, y, T, a.steps, a.warmup)
+    points = float(np.prod(case.shape))
+    gst = points * T / (ms * 1e-3) / 1e9
+    log("fused: %.3f ms/step (sweep %.3f ms), %.1f GStencil/s" % (ms, ms_sweep, gst))
+
+    plain_rec = None
+    if not a.no_plain:
+        plain = Plan(case.shape, case.r, case.kind, case.coeffs, case.bc, "f32", method="plain")
+        if not a.no_autotune:
+            plain.autotune()
+        pms, pms_sweep, _ = time_sweep(plain, x, y, T, max(2, a.steps // 2), 1)
+        plain_rec = {"value": points * T / (pms * 1e-3) / 1e9, "ms_per_step": pms,
+                     "kernel_ms_per_launch": pms_sweep / T,
+                     "hbm_frac": (2 * 4 * points / (pms_sweep / T * 1e-3) / 1e9) / HBM_PEAK_GBS,
+                     "config": plain.info()}
+        log("plain: %.3f ms/step, %.1f GStencil/s" % (pms, plain_rec["value"]))
+        plain.close()
+
+    # roofline of the dominant kernel (the fused pass): algorithmic bytes per launch
+    # = one read and one write of the field; its launches share the sweep time in
+    # proportion to the steps each advances
+    launch_ms = ms_sweep * k / T
+    alg_bytes = 2.0 * 4 * points
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        with open(PROFILE_TRAFFIC) as f:
+            prof = json.load(f)
+        if (prof.get("source_hash") == kernel_source_hash() and prof.get("k") == k and
+                prof.get("variant") == info["variant"] and prof.get("chunk") == info["tile"][2]):
+            traffic = prof.get("bytes_per_launch")
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "stream_kernel<float,3,R=1,star,K=%d> variant %d" % (k, info["variant"]),
+            "launch_ms": launch_ms}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("cpu baseline ...")
+        c32 = case.coeffs.astype(np.float32).astype(np.float64)
+        u32 = x.double().cpu().numpy()
+        cpu = cpu_baseline(u32, c32, case.r, case.kind, case.bc)
+        log("cpu: %.3f GStencil/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    rec = {
+        "metric": METRIC, "value": gst, "unit": "GStencil/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3D 7-point star r=1, %d^3 grid, FP32, zero halo, T=%d" % (n, T),
+                   "fused_k": k, "variant": info["variant"], "tile": info["tile"],
+                   "points": int(points), "T": T},
+        "sweep_ms_per_step": ms_sweep, "wall_ms_per_step": wall,
+        "plain": plain_rec,
+        "speedup_vs_plain": (plain_rec["ms_per_step"] / ms) if plain_rec else None,
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    fused.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,600 @@
+// api.cpp -- the C ABI: plans, sweeps, autotuning, reductions, errors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+#include "registry.hpp"
+#include "variants.hpp"
+
+namespace stn {
+
+static thread_local std::string t_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+void clear_error() { t_err.clear(); }
+
+int elem_bytes(int dtype) {
+    switch (dtype) {
+    case STENCIL_F64: return 8;
+    case STENCIL_F32: return 4;
+    case STENCIL_BF16:
+    case STENCIL_F16: return 2;
+    default: return 0;
+    }
+}
+
+// Canonical order: odometer over [-r, r]^dim with the last axis turning
+// fastest, keeping the members of the star or the box.
+int enumerate_offsets(int dim, int r, int kind, int32_t *out) {
+    int o[STENCIL_MAX_DIM];
+    for (int i = 0; i < dim; ++i) o[i] = -r;
+    int n = 0;
+    for (;;) {
+        int nonzero = 0;
+        for (int i = 0; i < dim; ++i) nonzero += (o[i] != 0);
+        if (kind == STENCIL_BOX || nonzero <= 1) {
+            if (out)
+                for (int i = 0; i < dim; ++i) out[n * dim + i] = o[i];
+            ++n;
+        }
+        int ax = dim - 1;
+        while (ax >= 0 && ++o[ax] > r) {
+            o[ax] = -r;
+            --ax;
+        }
+        if (ax < 0) break;
+    }
+    return n;
+}
+
+static bool shape_of(int dim, int variant, VariantShape *v) {
+    const int nv = dim == 3 ? kNumV3 : (dim == 2 ? kNumV2 : kNumV1);
+    if (variant < 1 || variant > nv) return false;
+    *v = dim == 3 ? kV3[variant] : (dim == 2 ? kV2[variant] : kV1[variant]);
+    return true;
+}
+
+static int box_key(const stencil_plan *p) { return p->dim == 1 ? 0 : (p->kind == STENCIL_BOX ? 1 : 0); }
+
+static int max_k_of(const stencil_plan *p, int variant) {
+    return registered_max_k(p->dtype, p->dim, p->r, box_key(p), variant);
+}
+
+static int num_variants_of(int dim) { return dim == 3 ? kNumV3 : (dim == 2 ? kNumV2 : kNumV1); }
+
+// 2D/3D fused kernels address one plane with 32-bit byte offsets (below
+// 2^31, the out-of-range marker) and need the x extent to be a multiple of
+// the lane width; the streamed extent must fit an int.
+static bool variant_fits_shape(const stencil_plan *p, int variant) {
+    VariantShape v;
+    if (!shape_of(p->dim, variant, &v)) return false;
+    if (p->dim == 1) return true;
+    const int64_t plane_bytes = p->n1 * p->n2 * elem_bytes(p->dtype);
+    if (plane_bytes >= ((int64_t)1 << 31) || p->n0 >= ((int64_t)1 << 31)) return false;
+    return v.vx == 1 || p->n2 % v.vx == 0;
+}
+
+static bool variant_fits_ptr(const stencil_plan *p, int variant, const void *a, const void *b) {
+    VariantShape v;
+    if (!shape_of(p->dim, variant, &v)) return false;
+    const uintptr_t al = (uintptr_t)v.vx * elem_bytes(p->dtype);
+    return v.vx == 1 || (((uintptr_t)a % al) == 0 && ((uintptr_t)b % al) == 0);
+}
+
+SweepLauncher pass_launcher(const stencil_plan *p, const Exec &ex, int k) {
+    if (ex.method == STENCIL_METHOD_GENERIC) return nullptr;
+    return find_launcher(KernelKey{p->dtype, p->dim, p->r, box_key(p), ex.variant, k});
+}
+
+// default variant: widest lanes that fit the shape, else the first registered
+static int default_variant(const stencil_plan *p, int need_k) {
+    int best = 0;
+    for (int v = 1; v <= num_variants_of(p->dim); ++v) {
+        if (!variant_fits_shape(p, v) || max_k_of(p, v) < need_k) continue;
+        VariantShape s;
+        shape_of(p->dim, v, &s);
+        if (best == 0) {
+            best = v;
+        } else {
+            VariantShape b;
+            shape_of(p->dim, best, &b);
+            // 1D/2D prefer wide lanes; 3D keeps the first listed (tuned default)
+            if (p->dim < 3 && s.vx > b.vx) best = v;
+        }
+    }
+    return best;
+}
+
+static int default_k(const stencil_plan *p, int variant) {
+    const int kmax = max_k_of(p, variant);
+    const int want = p->dim == 3 ? 4 : (p->dim == 2 ? 8 : 16);
+    return std::min(want, kmax);
+}
+
+// Resolve the requested method into an execution choice.  Returns a status.
+static int resolve_exec(stencil_plan *p) {
+    const stencil_opts &o = p->opts;
+    Exec ex{STENCIL_METHOD_GENERIC, 0, 1, 0};
+    int method = o.method;
+    if (method == STENCIL_METHOD_AUTO) {
+        method = default_variant(p, 1) ? STENCIL_METHOD_FUSED : STENCIL_METHOD_GENERIC;
+    }
+    if (method == STENCIL_METHOD_GENERIC) {
+        p->exec = ex;
+        return STENCIL_OK;
+    }
+    int variant = o.variant;
+    if (variant != 0) {
+        VariantShape v;
+        if (!shape_of(p->dim, variant, &v))
+            return fail(STENCIL_E_INVALID, "variant %d does not exist for %dD", variant, p->dim);
+        if (!variant_fits_shape(p, variant))
+            return fail(STENCIL_E_INVALID, "variant %d needs the last extent to be a multiple of %d",
+                        variant, v.vx);
+    } else {
+        variant = default_variant(p, 1);
+    }
+    if (variant == 0 || max_k_of(p, variant) < 1) {
+        if (o.method == STENCIL_METHOD_AUTO) {
+            p->exec = ex;
+            return STENCIL_OK;
+        }
+        return fail(STENCIL_E_UNSUPPORTED,
+                    "no fused kernel is compiled for this stencil (%dD r=%d %s dtype %d)", p->dim, p->r,
+                    p->kind == STENCIL_BOX ? "box" : "star", p->dtype);
+    }
+    int k = 1;
+    if (method == STENCIL_METHOD_FUSED) {
+        if (o.fused_k > 0) {
+            if (o.fused_k > max_k_of(p, variant))
+                return fail(STENCIL_E_UNSUPPORTED, "fused_k=%d exceeds the compiled maximum %d",
+                            o.fused_k, max_k_of(p, variant));
+            k = o.fused_k;
+        } else {
+            k = default_k(p, variant);
+        }
+    }
+    ex.method = method;
+    ex.variant = variant;
+    ex.k = k;
+    ex.chunk = o.chunk;
+    p->exec = ex;
+    return STENCIL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotune cache: signature -> best execution
+static std::mutex &tune_mutex() {
+    static std::mutex m;
+    return m;
+}
+static std::map<std::string, Exec> &tune_cache() {
+    static std::map<std::string, Exec> m;
+    return m;
+}
+static std::string signature(const stencil_plan *p) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "d%d r%d k%d bc%d t%d m%d %lld %lld %lld", p->dim, p->r, p->kind, p->bc,
+             p->dtype, p->opts.method, (long long)p->shape[0], (long long)p->shape[1],
+             (long long)p->shape[2]);
+    return buf;
+}
+
+int plan_prepare(stencil_plan *p, hipStream_t st) {
+    int dev = 0;
+    STN_HIP(hipGetDevice(&dev));
+    if (p->device >= 0) {
+        if (p->device != dev)
+            return fail(STENCIL_E_INVALID, "plan was prepared on device %d, current device is %d",
+                        p->device, dev);
+        return STENCIL_OK;
+    }
+    const size_t bytes = (size_t)p->points * elem_bytes(p->dtype);
+    void *s = nullptr;
+    STN_HIP(hipMalloc(&s, bytes));
+    // generic-kernel tables: offsets placed on the axes of the kernel view
+    // (n0, n1, n2) -- 3D (z, y, x), 2D (y, 1, x), 1D (1, 1, x) -- and weights in
+    // compute precision
+    static const int view_axis[4][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 1, 2}};
+    std::vector<int> off3(3 * p->npts, 0);
+    for (int j = 0; j < p->npts; ++j)
+        for (int i = 0; i < p->dim; ++i) off3[3 * j + view_axis[p->dim][i]] = p->offsets[j * p->dim + i];
+    int *d_off = nullptr;
+    void *d_coef = nullptr;
+    hipError_t e = hipMalloc(&d_off, off3.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&d_coef, (size_t)p->npts * 8);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_off, off3.data(), off3.size() * sizeof(int), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        if (p->dtype == STENCIL_F64) {
+            e = hipMemcpyAsync(d_coef, p->coeffs.data(), (size_t)p->npts * 8, hipMemcpyHostToDevice, st);
+        } else {
+            std::vector<float> cf(p->npts);
+            for (int j = 0; j < p->npts; ++j) cf[j] = (float)p->coeffs[j];
+            e = hipMemcpyAsync(d_coef, cf.data(), (size_t)p->npts * 4, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);  // cf leaves scope
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(s);
+        if (d_off) (void)hipFree(d_off);
+        if (d_coef) (void)hipFree(d_coef);
+        return fail(e == hipErrorOutOfMemory ? STENCIL_E_NOMEM : STENCIL_E_DEVICE,
+                    "plan device setup: %s", hipGetErrorString(e));
+    }
+    p->scratch[0] = s;
+    p->d_off = d_off;
+    p->d_coef = d_coef;
+    p->device = dev;
+    return STENCIL_OK;
+}
+
+int plan_alloc_alias(stencil_plan *p) {
+    if (p->scratch[1]) return STENCIL_OK;
+    const size_t bytes = (size_t)p->points * elem_bytes(p->dtype);
+    STN_HIP(hipMalloc(&p->scratch[1], bytes));
+    return STENCIL_OK;
+}
+
+static int launch_pass(stencil_plan *p, const Exec &ex, int k, const void *src, void *dst,
+                       hipStream_t st) {
+    if (ex.method == STENCIL_METHOD_GENERIC) {
+        const hipError_t e = launch_generic(p->dtype, src, dst, p->n0, p->n1, p->n2, p->npts, p->bc,
+                                            p->d_off, p->d_coef, st);
+        if (e != hipSuccess) return fail(STENCIL_E_DEVICE, "generic sweep launch: %s", hipGetErrorString(e));
+        return STENCIL_OK;
+    }
+    SweepLauncher fn = pass_launcher(p, ex, k);
+    if (!fn) return fail(STENCIL_E_UNSUPPORTED, "no kernel for variant %d with k=%d", ex.variant, k);
+    SweepLaunch L{src, dst, p->n0, p->n1, p->n2, p->bc, p->dense.data(), ex.chunk};
+    const hipError_t e = fn(L, st);
+    if (e != hipSuccess) return fail(STENCIL_E_DEVICE, "fused sweep launch (k=%d): %s", k, hipGetErrorString(e));
+    return STENCIL_OK;
+}
+
+int run_passes(stencil_plan *p, const Exec &ex, const void *src, void *dst, int64_t T, hipStream_t st) {
+    const size_t bytes = (size_t)p->points * elem_bytes(p->dtype);
+    if (T == 0) {
+        if (src != dst) STN_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+        return STENCIL_OK;
+    }
+    const int kk = ex.method == STENCIL_METHOD_GENERIC ? 1 : ex.k;
+    const int64_t full = T / kk;
+    const int rem = (int)(T % kk);
+    const int64_t P = full + (rem ? 1 : 0);
+    // buffers: b_0 = src, b_P = dst, b_i alternates dst / scratch backwards from P
+    const void *cur = src;
+    for (int64_t i = 1; i <= P; ++i) {
+        void *nxt = ((P - i) % 2 == 0) ? dst : p->scratch[0];
+        const int k = (i <= full) ? kk : rem;
+        const int rc = launch_pass(p, ex, k, cur, nxt, st);
+        if (rc != STENCIL_OK) return rc;
+        cur = nxt;
+    }
+    return STENCIL_OK;
+}
+
+// choose an execution whose lane width suits both pointers
+static Exec exec_for_ptrs(const stencil_plan *p, const void *a, const void *b) {
+    Exec ex = p->exec;
+    if (ex.method == STENCIL_METHOD_GENERIC || variant_fits_ptr(p, ex.variant, a, b)) return ex;
+    for (int v = 1; v <= num_variants_of(p->dim); ++v) {
+        if (variant_fits_ptr(p, v, a, b) && max_k_of(p, v) >= ex.k) {
+            ex.variant = v;
+            return ex;
+        }
+    }
+    ex.method = STENCIL_METHOD_GENERIC;
+    ex.variant = 0;
+    ex.k = 1;
+    return ex;
+}
+
+static int time_exec(stencil_plan *p, const Exec &ex, hipStream_t st, float *ms_per_step) {
+    hipEvent_t e0, e1;
+    STN_HIP(hipEventCreate(&e0));
+    STN_HIP(hipEventCreate(&e1));
+    int rc = STENCIL_OK;
+    float best = 1e30f;
+    for (int rep = 0; rep < 4 && rc == STENCIL_OK; ++rep) {
+        (void)hipEventRecord(e0, st);
+        rc = launch_pass(p, ex, ex.k, p->scratch[0], p->scratch[1], st);
+        (void)hipEventRecord(e1, st);
+        if (rc != STENCIL_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(STENCIL_E_DEVICE, "autotune timing failed");
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) best = std::min(best, ms);  // first run warms up
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_step = best / (float)ex.k;
+    return rc;
+}
+
+static int autotune_impl(stencil_plan *p, hipStream_t st) {
+    if (p->exec.method == STENCIL_METHOD_GENERIC) {
+        p->tuned = 1;
+        return STENCIL_OK;
+    }
+    const std::string sig = signature(p);
+    {
+        std::lock_guard<std::mutex> g(tune_mutex());
+        auto it = tune_cache().find(sig);
+        if (it != tune_cache().end()) {
+            p->exec = it->second;
+            p->tuned = 1;
+            return STENCIL_OK;
+        }
+    }
+    int rc = plan_prepare(p, st);
+    if (rc != STENCIL_OK) return rc;
+    rc = plan_alloc_alias(p);
+    if (rc != STENCIL_OK) return rc;
+    STN_HIP(hipMemsetAsync(p->scratch[0], 0, (size_t)p->points * elem_bytes(p->dtype), st));
+    Exec best = p->exec;
+    float best_ms = 1e30f;
+    const bool plain = p->exec.method == STENCIL_METHOD_PLAIN;
+    const bool fixed_k = p->opts.fused_k > 0;
+    const bool fixed_v = p->opts.variant > 0;
+    for (int v = 1; v <= num_variants_of(p->dim); ++v) {
+        if (fixed_v && v != p->opts.variant) continue;
+        if (!variant_fits_shape(p, v)) continue;
+        const int kmax = max_k_of(p, v);
+        for (int k = 1; k <= kmax; ++k) {
+            if (plain && k != 1) continue;
+            if (fixed_k && k != p->opts.fused_k) continue;
+            std::vector<int> chunks{p->opts.chunk};
+            if (p->dim >= 2 && p->opts.chunk == 0) {
+                for (int c : {16, 32, 64, 128, 256, 512})
+                    if (c >= 2 * k * (2 * p->r + 1) && c < p->n0) chunks.push_back(c);
+            }
+            for (int c : chunks) {
+                Exec ex{p->exec.method, v, k, c};
+                float ms = 0;
+                rc = time_exec(p, ex, st, &ms);
+                if (rc != STENCIL_OK) return rc;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = ex;
+                }
+            }
+        }
+    }
+    p->exec = best;
+    p->tuned = 1;
+    std::lock_guard<std::mutex> g(tune_mutex());
+    tune_cache()[sig] = best;
+    return STENCIL_OK;
+}
+
+static int check_plan(const stencil_plan *p) {
+    if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
+    return STENCIL_OK;
+}
+
+}  // namespace stn
+
+using namespace stn;
+
+extern "C" {
+
+int stencil_version(void) { return STENCIL_VERSION; }
+
+const char *stencil_last_error(void) { return t_err.c_str(); }
+
+int stencil_num_points(int dim, int radius, int kind) {
+    clear_error();
+    if (dim < 1 || dim > STENCIL_MAX_DIM) return fail(STENCIL_E_INVALID, "dim must be 1..3 (got %d)", dim);
+    if (radius < 1) return fail(STENCIL_E_INVALID, "radius must be >= 1 (got %d)", radius);
+    if (kind != STENCIL_STAR && kind != STENCIL_BOX) return fail(STENCIL_E_INVALID, "unknown kind %d", kind);
+    if (kind == STENCIL_STAR) return 2 * dim * radius + 1;
+    int n = 1;
+    for (int i = 0; i < dim; ++i) n *= 2 * radius + 1;
+    return n;
+}
+
+int stencil_offsets(int dim, int radius, int kind, int32_t *out) {
+    const int n = stencil_num_points(dim, radius, kind);
+    if (n < 0) return n;
+    if (!out) return fail(STENCIL_E_INVALID, "out is NULL");
+    return enumerate_offsets(dim, radius, kind, out);
+}
+
+int stencil_plan_create(stencil_plan **out, int dim, const int64_t *shape, int radius, int kind,
+                        const double *coeffs, int ncoeffs, int bc, int dtype, const stencil_opts *opts) {
+    clear_error();
+    if (!out) return fail(STENCIL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const int npts = stencil_num_points(dim, radius, kind);
+    if (npts < 0) return npts;
+    if (radius > STENCIL_MAX_RADIUS)
+        return fail(STENCIL_E_UNSUPPORTED, "radius %d exceeds the maximum %d", radius, STENCIL_MAX_RADIUS);
+    if (!shape) return fail(STENCIL_E_INVALID, "shape is NULL");
+    if (!coeffs) return fail(STENCIL_E_INVALID, "coeffs is NULL");
+    if (ncoeffs != npts)
+        return fail(STENCIL_E_INVALID, "ncoeffs=%d but the stencil has %d points", ncoeffs, npts);
+    if (bc != STENCIL_BC_ZERO && bc != STENCIL_BC_PERIODIC) return fail(STENCIL_E_INVALID, "unknown bc %d", bc);
+    if (elem_bytes(dtype) == 0) return fail(STENCIL_E_INVALID, "unknown dtype %d", dtype);
+    int64_t points = 1;
+    for (int i = 0; i < dim; ++i) {
+        if (shape[i] < 1) return fail(STENCIL_E_INVALID, "shape[%d]=%lld must be >= 1", i, (long long)shape[i]);
+        if (shape[i] > ((int64_t)1 << 40) || points > ((int64_t)1 << 46) / shape[i])
+            return fail(STENCIL_E_INVALID, "grid too large");
+        points *= shape[i];
+    }
+    if (opts) {
+        if (opts->method < STENCIL_METHOD_AUTO || opts->method > STENCIL_METHOD_GENERIC)
+            return fail(STENCIL_E_INVALID, "unknown method %d", opts->method);
+        if (opts->fused_k < 0) return fail(STENCIL_E_INVALID, "fused_k must be >= 0");
+        if (opts->variant < 0) return fail(STENCIL_E_INVALID, "variant must be >= 0");
+        if (opts->chunk < 0) return fail(STENCIL_E_INVALID, "chunk must be >= 0");
+    }
+    stencil_plan *p = new (std::nothrow) stencil_plan();
+    if (!p) return fail(STENCIL_E_NOMEM, "out of host memory");
+    p->dim = dim;
+    p->r = radius;
+    p->kind = kind;
+    p->bc = bc;
+    p->dtype = dtype;
+    p->npts = npts;
+    for (int i = 0; i < 3; ++i) p->shape[i] = i < dim ? shape[i] : 0;
+    p->points = points;
+    if (dim == 3) {
+        p->n0 = shape[0];
+        p->n1 = shape[1];
+        p->n2 = shape[2];
+    } else if (dim == 2) {
+        p->n0 = shape[0];
+        p->n1 = 1;
+        p->n2 = shape[1];
+    } else {
+        p->n0 = 1;
+        p->n1 = 1;
+        p->n2 = shape[0];
+    }
+    p->offsets.resize((size_t)npts * dim);
+    enumerate_offsets(dim, radius, kind, p->offsets.data());
+    p->coeffs.assign(coeffs, coeffs + npts);
+    const int W = 2 * radius + 1;
+    int ndense = 1;
+    for (int i = 0; i < dim; ++i) ndense *= W;
+    p->dense.assign(ndense, 0.0);
+    for (int j = 0; j < npts; ++j) {
+        int idx = 0;
+        for (int i = 0; i < dim; ++i) idx = idx * W + (p->offsets[j * dim + i] + radius);
+        p->dense[idx] = coeffs[j];
+    }
+    p->opts = opts ? *opts : stencil_opts{0, 0, 0, 0, 0};
+    p->tuned = 0;
+    p->device = -1;
+    p->scratch[0] = p->scratch[1] = nullptr;
+    p->d_off = nullptr;
+    p->d_coef = nullptr;
+    const int rc = resolve_exec(p);
+    if (rc != STENCIL_OK) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return STENCIL_OK;
+}
+
+void stencil_plan_destroy(stencil_plan *p) {
+    if (!p) return;
+    if (p->scratch[0]) (void)hipFree(p->scratch[0]);
+    if (p->scratch[1]) (void)hipFree(p->scratch[1]);
+    if (p->d_off) (void)hipFree(p->d_off);
+    if (p->d_coef) (void)hipFree(p->d_coef);
+    delete p;
+}
+
+int stencil_plan_info(const stencil_plan *p, stencil_plan_desc *out) {
+    clear_error();
+    if (check_plan(p) != STENCIL_OK) return STENCIL_E_INVALID;
+    if (!out) return fail(STENCIL_E_INVALID, "out is NULL");
+    std::memset(out, 0, sizeof *out);
+    out->dim = p->dim;
+    out->radius = p->r;
+    out->kind = p->kind;
+    out->bc = p->bc;
+    out->dtype = p->dtype;
+    out->npts = p->npts;
+    for (int i = 0; i < 3; ++i) out->shape[i] = p->shape[i];
+    out->points = p->points;
+    out->method = p->exec.method;
+    out->fused_k = p->exec.method == STENCIL_METHOD_GENERIC ? 1 : p->exec.k;
+    out->variant = p->exec.variant;
+    out->elem_bytes = elem_bytes(p->dtype);
+    if (p->exec.method != STENCIL_METHOD_GENERIC) {
+        VariantShape v;
+        if (shape_of(p->dim, p->exec.variant, &v)) {
+            const Geometry g = p->dim == 1 ? seg1d_geometry(p->r, p->exec.k, v, p->n2)
+                                           : stream_geometry(p->dim, p->r, p->exec.k, v, p->n0, p->n1,
+                                                             p->n2, p->exec.chunk);
+            out->tile[0] = g.out_x;
+            out->tile[1] = p->dim == 3 ? g.out_y : 0;
+            out->tile[2] = p->dim >= 2 ? g.chunk : 0;
+        }
+    }
+    const int64_t field = p->points * elem_bytes(p->dtype);
+    out->scratch_bytes = (p->scratch[0] ? field : 0) + (p->scratch[1] ? field : 0);
+    out->tuned = p->tuned;
+    return STENCIL_OK;
+}
+
+int stencil_plan_prepare(stencil_plan *p, void *stream) {
+    clear_error();
+    if (check_plan(p) != STENCIL_OK) return STENCIL_E_INVALID;
+    return plan_prepare(p, (hipStream_t)stream);
+}
+
+int stencil_autotune(stencil_plan *p, void *stream) {
+    clear_error();
+    if (check_plan(p) != STENCIL_OK) return STENCIL_E_INVALID;
+    return autotune_impl(p, (hipStream_t)stream);
+}
+
+int stencil_run(stencil_plan *p, const void *d_in, void *d_out, int64_t T, void *stream) {
+    clear_error();
+    if (check_plan(p) != STENCIL_OK) return STENCIL_E_INVALID;
+    if (!d_in || !d_out) return fail(STENCIL_E_INVALID, "d_in and d_out must not be NULL");
+    if (T < 0) return fail(STENCIL_E_INVALID, "T must be >= 0 (got %lld)", (long long)T);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = plan_prepare(p, st);
+    if (rc != STENCIL_OK) return rc;
+    if (p->opts.autotune && !p->tuned) {
+        rc = autotune_impl(p, st);
+        if (rc != STENCIL_OK) return rc;
+    }
+    const void *src = d_in;
+    if (d_in == d_out && T > 0) {
+        rc = plan_alloc_alias(p);
+        if (rc != STENCIL_OK) return rc;
+        STN_HIP(hipMemcpyAsync(p->scratch[1], d_in, (size_t)p->points * elem_bytes(p->dtype),
+                               hipMemcpyDeviceToDevice, st));
+        src = p->scratch[1];
+    }
+    const Exec ex = exec_for_ptrs(p, src, d_out);
+    return run_passes(p, ex, src, d_out, T, st);
+}
+
+int stencil_reduce(int dtype, const void *d_u, const void *d_ref, int64_t n, double *d_out, void *stream) {
+    clear_error();
+    if (elem_bytes(dtype) == 0) return fail(STENCIL_E_INVALID, "unknown dtype %d", dtype);
+    if (n < 0) return fail(STENCIL_E_INVALID, "n must be >= 0");
+    if (!d_out || (!d_u && n > 0)) return fail(STENCIL_E_INVALID, "NULL pointer");
+    // stream-ordered partials: concurrent reductions on different streams never share them
+    hipStream_t st = (hipStream_t)stream;
+    double *part = nullptr;
+    STN_HIP(hipMallocAsync((void **)&part, reduce_partials_bytes(), st));
+    const hipError_t e = launch_reduce(dtype, d_u, d_ref, n, part, d_out, st);
+    const hipError_t f = hipFreeAsync(part, st);
+    if (e != hipSuccess) return fail(STENCIL_E_DEVICE, "reduction launch: %s", hipGetErrorString(e));
+    if (f != hipSuccess) return fail(STENCIL_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(f));
+    return STENCIL_OK;
+}
+
+}  // extern "C"

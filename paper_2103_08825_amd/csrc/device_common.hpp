@@ -1,0 +1,179 @@
+// device_common.hpp -- gfx950 device helpers shared by the stencil kernels:
+// storage <-> compute conversions, whole-wave DPP lane shifts, compile-time
+// loops, and the XCD-aware workgroup remap.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+#include <utility>
+
+namespace stn {
+
+// ---------------------------------------------------------------------------
+// Storage types.  bf16 is kept as its raw 16 bits; fp16 uses _Float16.
+struct bf16_t {
+    uint16_t bits;
+};
+
+template <typename S> struct ComputeOf { using type = float; };
+template <> struct ComputeOf<double> { using type = double; };
+
+__device__ __forceinline__ float to_compute(float v) { return v; }
+__device__ __forceinline__ double to_compute(double v) { return v; }
+__device__ __forceinline__ float to_compute(_Float16 v) { return (float)v; }
+__device__ __forceinline__ float to_compute(bf16_t v) {
+    return __uint_as_float(((uint32_t)v.bits) << 16);
+}
+
+template <typename S> __device__ __forceinline__ S from_compute(float v);
+template <typename S> __device__ __forceinline__ S from_compute(double v);
+template <> __device__ __forceinline__ float from_compute<float>(float v) { return v; }
+template <> __device__ __forceinline__ double from_compute<double>(double v) { return v; }
+template <> __device__ __forceinline__ _Float16 from_compute<_Float16>(float v) {
+    return (_Float16)v;  // v_cvt_f16_f32, round to nearest even
+}
+template <> __device__ __forceinline__ bf16_t from_compute<bf16_t>(float v) {
+    // round to nearest even on the upper 16 bits; NaN stays a quiet NaN
+    uint32_t u = __float_as_uint(v);
+    bf16_t r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+        r.bits = (uint16_t)((u >> 16) | 0x0040u);
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);
+        r.bits = (uint16_t)(u >> 16);
+    }
+    return r;
+}
+
+__device__ __forceinline__ float fma_c(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_c(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// VX consecutive storage elements, aligned so one vector load/store moves them.
+template <typename S, int VX> struct alignas(sizeof(S) * VX) VecS {
+    S v[VX];
+};
+
+// ---------------------------------------------------------------------------
+// Whole-wavefront lane shifts (DPP wave_shr:1 / wave_shl:1).  Lane l receives
+// the value of lane l-1 (shr) or l+1 (shl); with bound_ctrl set, the lane that
+// has no source reads 0.
+template <int CTRL> __device__ __forceinline__ float dpp32(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp32(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+constexpr int kDppWaveShr1 = 0x138;  // from lane - 1
+constexpr int kDppWaveShl1 = 0x130;  // from lane + 1
+
+// value held by lane (l + S) of the wave (0 outside the wave)
+template <int S, typename C> __device__ __forceinline__ C lane_shift(C v) {
+    if constexpr (S == 0) {
+        return v;
+    } else if constexpr (S < 0) {
+        return lane_shift<S + 1>(dpp32<kDppWaveShr1>(v));
+    } else {
+        return lane_shift<S - 1>(dpp32<kDppWaveShl1>(v));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Buffer (range-checked) loads and stores.  A resource covers one plane of a
+// grid; offsets at or beyond its size read as 0 and drop stores, which is how
+// the kernels handle points outside the grid without branches.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kBufferFlags = 0x00020000;  // raw 32-bit dword access (gfx9 family)
+constexpr uint32_t kOutOfRange = 0x80000000u;  // byte offset beyond every resource
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufferFlags);
+}
+
+template <int BYTES> struct BufWord;
+template <> struct BufWord<2> { using T = unsigned short; };
+template <> struct BufWord<4> { using T = unsigned int; };
+template <> struct BufWord<8> { using T = __attribute__((ext_vector_type(2))) unsigned int; };
+template <> struct BufWord<16> { using T = __attribute__((ext_vector_type(4))) unsigned int; };
+
+template <int BYTES> __device__ __forceinline__ typename BufWord<BYTES>::T buf_load(rsrc_t r, uint32_t off) {
+    if constexpr (BYTES == 2) return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+    if constexpr (BYTES == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+    if constexpr (BYTES == 8) return __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    if constexpr (BYTES == 16) return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+}
+template <int BYTES> __device__ __forceinline__ void buf_store(typename BufWord<BYTES>::T v, rsrc_t r, uint32_t off) {
+    if constexpr (BYTES == 2) __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, 0, 0);
+    if constexpr (BYTES == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)off, 0, 0);
+    if constexpr (BYTES == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+    if constexpr (BYTES == 16) __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, 0);
+}
+
+// VX consecutive elements of type S through buffer instructions (<= 16 bytes per
+// instruction; wider vectors are split)
+template <typename S, int VX> __device__ __forceinline__ VecS<S, VX> vec_load(rsrc_t r, uint32_t off) {
+    constexpr int B = (int)sizeof(S) * VX;
+    if constexpr (B <= 16) {
+        return __builtin_bit_cast(VecS<S, VX>, buf_load<B>(r, off));
+    } else {
+        VecS<S, VX> out;
+        constexpr int H = VX / 2;
+        const VecS<S, H> lo = vec_load<S, H>(r, off);
+        const VecS<S, H> hi = vec_load<S, H>(r, off == kOutOfRange ? off : off + 16u);
+#pragma unroll
+        for (int v = 0; v < H; ++v) {
+            out.v[v] = lo.v[v];
+            out.v[H + v] = hi.v[v];
+        }
+        return out;
+    }
+}
+template <typename S, int VX> __device__ __forceinline__ void vec_store(const VecS<S, VX> &t, rsrc_t r, uint32_t off) {
+    constexpr int B = (int)sizeof(S) * VX;
+    if constexpr (B <= 16) {
+        buf_store<B>(__builtin_bit_cast(typename BufWord<B>::T, t), r, off);
+    } else {
+        constexpr int H = VX / 2;
+        VecS<S, H> lo, hi;
+#pragma unroll
+        for (int v = 0; v < H; ++v) {
+            lo.v[v] = t.v[v];
+            hi.v[v] = t.v[H + v];
+        }
+        vec_store<S, H>(lo, r, off);
+        vec_store<S, H>(hi, r, off == kOutOfRange ? off : off + 16u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time loops: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, typename F> __device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+constexpr int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+constexpr int posmod(int a, int b) { return ((a % b) + b) % b; }
+
+// ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Remap the hardware block id so every XCD gets a contiguous range of
+// logical tiles; neighbouring tiles then share halo reads through one L2.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int q = n / kNumXcd, rem = n % kNumXcd;
+    const int xcd = b % kNumXcd, idx = b / kNumXcd;
+    return xcd < rem ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
+}
+
+__device__ __forceinline__ int64_t wrap_index(int64_t i, int64_t n) {
+    int64_t m = i % n;
+    return m < 0 ? m + n : m;
+}
+
+}  // namespace stn

@@ -1,0 +1,98 @@
+// launch.hpp -- host-side geometry and launch templates for the sweep kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernel_args.hpp"
+
+namespace stn {
+
+enum Dtype { kF64 = 0, kF32 = 1, kBF16 = 2, kF16 = 3 };
+
+// One fused launch: K steps from src to dst.
+struct SweepLaunch {
+    const void *src;
+    void *dst;
+    int64_t n0, n1, n2;  // streamed axis, y axis (1 in 2D), x axis; 1D uses n2 only
+    int bc;
+    const double *dense; // dense weight table: [dz][dy][dx] (3D), [dz][dx] (2D), [dx] (1D)
+    int chunk;           // planes per workgroup along axis 0; 0 = automatic
+};
+
+using SweepLauncher = hipError_t (*)(const SweepLaunch &, hipStream_t);
+
+// Kernel shape of a fused variant.
+struct VariantShape {
+    int vx, nw, rw;
+};
+
+// Output tiling of one fused launch.
+struct Geometry {
+    int tiles_x, tiles_y, chunks, chunk, out_x, out_y, halo_x, nblocks, threads;
+    bool ok;
+};
+
+inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+inline Geometry stream_geometry(int dim, int r, int k, VariantShape v, int64_t n0, int64_t n1,
+                                int64_t n2, int chunk) {
+    Geometry g{};
+    g.threads = 64 * v.nw;
+    g.halo_x = round_up(k * r, v.vx);
+    g.out_x = 64 * v.vx - 2 * g.halo_x;
+    g.out_y = (dim == 3) ? v.nw * v.rw - 2 * k * r : 1;
+    if (g.out_x <= 0 || g.out_y <= 0) return g;
+    g.tiles_x = (int)((n2 + g.out_x - 1) / g.out_x);
+    g.tiles_y = (dim == 3) ? (int)((n1 + g.out_y - 1) / g.out_y) : 1;
+    int64_t nxy = (dim == 3) ? (int64_t)g.tiles_x * g.tiles_y : (g.tiles_x + v.nw - 1) / v.nw;
+    if (chunk <= 0) {
+        // aim at ~2048 workgroups, keeping the per-chunk fill (K*(2R+1) extra
+        // steps) below a quarter of the chunk
+        int64_t want = (2048 + nxy - 1) / nxy;
+        int64_t c = (n0 + want - 1) / want;
+        int64_t cmin = 4 * (int64_t)k * (2 * r + 1);
+        if (c < cmin) c = cmin;
+        if (c > n0) c = n0;
+        chunk = (int)c;
+    }
+    g.chunk = chunk;
+    g.chunks = (int)((n0 + chunk - 1) / chunk);
+    const int64_t nb = nxy * g.chunks;
+    if (nb <= 0 || nb > 0x7fffffff) return g;
+    g.nblocks = (int)nb;
+    g.ok = true;
+    return g;
+}
+
+inline Geometry seg1d_geometry(int r, int k, VariantShape v, int64_t n) {
+    Geometry g{};
+    g.threads = 64 * v.nw;
+    g.halo_x = round_up(k * r, v.vx);
+    g.out_x = 64 * v.vx - 2 * g.halo_x;
+    if (g.out_x <= 0) return g;
+    const int64_t tiles = (n + g.out_x - 1) / g.out_x;
+    if (tiles > 0x7fffffff) return g;
+    g.tiles_x = (int)tiles;
+    g.tiles_y = 1;
+    g.chunks = 1;
+    g.chunk = 1;
+    g.out_y = 1;
+    g.nblocks = (g.tiles_x + v.nw - 1) / v.nw;
+    g.ok = g.nblocks > 0;
+    return g;
+}
+
+// Registry lookups, defined in the instantiation units.  Return nullptr
+// when no kernel is compiled for the combination.
+SweepLauncher find_stream(int dtype, int dim, int r, bool box, int variant, int k);
+SweepLauncher find_seg1d(int dtype, int r, int variant, int k);
+bool variant_shape(int dim, int variant, VariantShape *out);
+int num_variants(int dim);
+int max_fused_k(int dim);
+
+hipError_t launch_generic(int dtype, const void *src, void *dst, int64_t n0, int64_t n1,
+                          int64_t n2, int npts, int bc, const int *d_off, const void *d_coef,
+                          hipStream_t st);
+
+}  // namespace stn

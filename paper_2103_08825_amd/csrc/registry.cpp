@@ -1,0 +1,62 @@
+// registry.cpp -- process-wide table of compiled fused-kernel launchers.
+#include "registry.hpp"
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+namespace stn {
+namespace {
+
+using Key = std::tuple<int, int, int, int, int, int>;
+
+std::mutex &reg_mutex() {
+    static std::mutex m;
+    return m;
+}
+std::map<Key, SweepLauncher> &reg_map() {
+    static std::map<Key, SweepLauncher> m;
+    return m;
+}
+Key tup(const KernelKey &k) { return Key(k.dtype, k.dim, k.r, k.box, k.variant, k.k); }
+
+}  // namespace
+
+void register_launcher(const KernelKey &key, SweepLauncher fn) {
+    std::lock_guard<std::mutex> g(reg_mutex());
+    reg_map()[tup(key)] = fn;
+}
+
+SweepLauncher find_launcher(const KernelKey &key) {
+    std::lock_guard<std::mutex> g(reg_mutex());
+    auto it = reg_map().find(tup(key));
+    return it == reg_map().end() ? nullptr : it->second;
+}
+
+int registered_max_k(int dtype, int dim, int r, int box, int variant) {
+    std::lock_guard<std::mutex> g(reg_mutex());
+    int best = 0;
+    for (const auto &kv : reg_map()) {
+        const Key &k = kv.first;
+        if (std::get<0>(k) == dtype && std::get<1>(k) == dim && std::get<2>(k) == r &&
+            std::get<3>(k) == box && std::get<4>(k) == variant && std::get<5>(k) > best)
+            best = std::get<5>(k);
+    }
+    return best;
+}
+
+int registered_keys(KernelKey *out, int cap) {
+    std::lock_guard<std::mutex> g(reg_mutex());
+    int n = 0;
+    for (const auto &kv : reg_map()) {
+        if (out && n < cap) {
+            const Key &k = kv.first;
+            out[n] = KernelKey{std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                               std::get<3>(k), std::get<4>(k), std::get<5>(k)};
+        }
+        ++n;
+    }
+    return n;
+}
+
+}  // namespace stn

@@ -1,0 +1,27 @@
+// registry.hpp -- lookup of the compiled fused kernels.
+//
+// Each instantiation unit registers its launchers from a static initialiser
+// when the library is loaded; plans look them up by
+// (dtype, dim, radius, box, variant, k).
+#pragma once
+
+#include "launch.hpp"
+
+namespace stn {
+
+struct KernelKey {
+    int dtype, dim, r, box, variant, k;
+};
+
+void register_launcher(const KernelKey &key, SweepLauncher fn);
+SweepLauncher find_launcher(const KernelKey &key);
+// largest k registered for (dtype, dim, r, box, variant); 0 if none
+int registered_max_k(int dtype, int dim, int r, int box, int variant);
+// every registered key
+int registered_keys(KernelKey *out, int cap);
+
+template <typename S> constexpr int dtype_of();
+template <> constexpr int dtype_of<double>() { return kF64; }
+template <> constexpr int dtype_of<float>() { return kF32; }
+
+}  // namespace stn
