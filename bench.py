@@ -3,9 +3,10 @@ and the FP64 CPU oracle.
 
 Workload: 3D 7-point star (r = 1), 512^3 grid, FP32 storage and arithmetic,
 zero halo, T = 64 steps, seeded normalised weights and a U[-1, 1) field.
-One timed step = one whole sweep (stencil_run, T = 64, with the tuned fused
-depth k, tile variant and z-chunk) followed by the FP64 checksum reduction of
-u_T, inputs resident in HBM.  The plain one-step-per-launch sweep (k = 1) is
+One timed step = one whole sweep (stencil_run, T = 64, with the library's
+measured default fused depth k, tile variant and z-chunk, or the autotuned
+ones with --autotune) followed by the FP64 checksum reduction of u_T, inputs
+resident in HBM.  The plain one-step-per-launch sweep (k = 1) is
 timed the same way for the speedup.
 
 Prints one JSON line.  Usage:
@@ -93,10 +94,15 @@ def main(argv=None):
     ap.add_argument("--T", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every compiled (variant, k, chunk) first instead of the "
+                         "library's measured default")
     ap.add_argument("--fused-k", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy the FP32 field (2 x 512 MiB moved per copy) --steps times; "
+                         "used to scale the HBM byte counters")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print("bench.py measures one GPU: the sweep of one grid runs on one device; "
@@ -111,6 +117,22 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     n, T = a.n, a.T
+    if a.copy_calibration:
+        x = torch.rand((n, n, n), device="cuda", dtype=torch.float32)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        nbytes = 2 * x.numel() * 4
+        print(json.dumps({"copy_bytes": nbytes, "ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9}),
+              flush=True)
+        return 0
     case = W.case_3d("3d7p", seed=0, n=n, T=T)
     log("inputs: %s %s T=%d" % (case.name, case.shape, T))
     x = torch.from_numpy(case.u0).to(torch.float32).cuda()
@@ -118,11 +140,12 @@ def main(argv=None):
 
     fused = Plan(case.shape, case.r, case.kind, case.coeffs, case.bc, "f32", method="fused",
                  fused_k=a.fused_k, variant=a.variant, chunk=a.chunk)
-    if not a.no_autotune:
+    if a.autotune:
         t0 = time.time()
         fused.autotune()
         log("autotune (fused) %.1fs -> %s" % (time.time() - t0, fused.info()))
     info = fused.info()
+    log("fused plan: %s" % info)
     k = info["fused_k"]
     ms, ms_sweep, wall = time_sweep(fused, x, y, T, a.steps, a.warmup)
     points = float(np.prod(case.shape))
@@ -132,7 +155,7 @@ def main(argv=None):
     plain_rec = None
     if not a.no_plain:
         plain = Plan(case.shape, case.r, case.kind, case.coeffs, case.bc, "f32", method="plain")
-        if not a.no_autotune:
+        if a.autotune:
             plain.autotune()
         pms, pms_sweep, _ = time_sweep(plain, x, y, T, max(2, a.steps // 2), 1)
         plain_rec = {"value": points * T / (pms * 1e-3) / 1e9, "ms_per_step": pms,

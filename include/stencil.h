@@ -187,7 +187,8 @@ int stencil_adjoint(stencil_plan *p, const void *d_u0, const void *d_gT, int64_t
  * FP64 into d_out[6] (device doubles):
  *   [0] sum u   [1] sum u^2   [2] max |u|
  *   [3] sum (u-ref)^2   [4] max |u-ref|   [5] max |ref|   (0 when d_ref is NULL)
- * The result is deterministic for a given n (fixed partial layout). */
+ * The result is deterministic for a given n and pointer alignment (fixed
+ * partial layout; vector loads when both pointers are 4-element aligned). */
 int stencil_reduce(int dtype, const void *d_u, const void *d_ref, int64_t n, double *d_out,
                    void *stream);
 

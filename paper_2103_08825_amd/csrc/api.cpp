@@ -129,6 +129,30 @@ static int default_k(const stencil_plan *p, int variant) {
     return std::min(want, kmax);
 }
 
+// Measured defaults (MI355X, 512^3 3D and 8192^2 2D grids; each the fastest
+// (variant, k, chunk) of a sweep over all compiled choices).  Shape-independent;
+// stencil_autotune refines them for a given plan.
+struct Choice {
+    int dim, r, kind, dclass;  // dclass: 0 FP64, 1 FP32, 2 16-bit
+    int variant, k, chunk;     // fused
+    int pvariant, pchunk;      // plain (k = 1)
+};
+static const Choice kChoices[] = {
+    {3, 1, STENCIL_STAR, 1, 4, 4, 64, 2, 0},  {3, 1, STENCIL_BOX, 1, 1, 2, 32, 2, 0},
+    {3, 2, STENCIL_STAR, 1, 1, 2, 64, 1, 32}, {3, 1, STENCIL_STAR, 2, 1, 2, 32, 1, 32},
+    {3, 1, STENCIL_BOX, 2, 1, 2, 32, 1, 32},  {3, 2, STENCIL_STAR, 2, 1, 2, 64, 1, 32},
+    {3, 1, STENCIL_STAR, 0, 1, 2, 0, 1, 32},  {3, 1, STENCIL_BOX, 0, 1, 2, 0, 1, 32},
+    {3, 2, STENCIL_STAR, 0, 1, 2, 0, 1, 32},  {2, 1, STENCIL_STAR, 1, 2, 7, 64, 2, 64},
+    {2, 1, STENCIL_BOX, 1, 2, 5, 0, 2, 64},
+};
+
+static const Choice *measured_choice(const stencil_plan *p) {
+    const int dclass = p->dtype == STENCIL_F64 ? 0 : (p->dtype == STENCIL_F32 ? 1 : 2);
+    for (const Choice &c : kChoices)
+        if (c.dim == p->dim && c.r == p->r && c.kind == p->kind && c.dclass == dclass) return &c;
+    return nullptr;
+}
+
 // Resolve the requested method into an execution choice.  Returns a status.
 static int resolve_exec(stencil_plan *p) {
     const stencil_opts &o = p->opts;
@@ -152,6 +176,15 @@ static int resolve_exec(stencil_plan *p) {
     } else {
         variant = default_variant(p, 1);
     }
+    const Choice *mc = measured_choice(p);
+    int chunk = o.chunk;
+    if (mc && o.variant == 0) {
+        const int mv = method == STENCIL_METHOD_PLAIN ? mc->pvariant : mc->variant;
+        if (variant_fits_shape(p, mv) && max_k_of(p, mv) >= 1) {
+            variant = mv;
+            if (o.chunk == 0) chunk = method == STENCIL_METHOD_PLAIN ? mc->pchunk : mc->chunk;
+        }
+    }
     if (variant == 0 || max_k_of(p, variant) < 1) {
         if (o.method == STENCIL_METHOD_AUTO) {
             p->exec = ex;
@@ -170,12 +203,13 @@ static int resolve_exec(stencil_plan *p) {
             k = o.fused_k;
         } else {
             k = default_k(p, variant);
+            if (mc && variant == mc->variant && mc->k <= max_k_of(p, variant)) k = mc->k;
         }
     }
     ex.method = method;
     ex.variant = variant;
     ex.k = k;
-    ex.chunk = o.chunk;
+    ex.chunk = chunk;
     p->exec = ex;
     return STENCIL_OK;
 }

@@ -7,7 +7,7 @@
 
 namespace stn {
 
-constexpr int kReduceBlocks = 1024;
+constexpr int kReduceBlocks = 2048;  // partial slots (a launch uses <= this many)
 constexpr int kReduceThreads = 256;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -21,70 +21,131 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-template <typename S>
-__global__ void __launch_bounds__(kReduceThreads)
-    reduce_partials(const S *__restrict__ u, const S *__restrict__ ref, int64_t n, double *part) {
-    double s = 0, s2 = 0, mx = 0, d2 = 0, dmx = 0, rmx = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double a = (double)to_compute(u[i]);
-        s += a;
-        s2 += a * a;
-        mx = fmax(mx, fabs(a));
-        if (ref) {
-            const double b = (double)to_compute(ref[i]);
-            const double d = a - b;
-            d2 += d * d;
-            dmx = fmax(dmx, fabs(d));
-            rmx = fmax(rmx, fabs(b));
-        }
-    }
-    __shared__ double sh[6][kReduceThreads / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    s = wave_sum(s);
-    s2 = wave_sum(s2);
-    mx = wave_max(mx);
-    d2 = wave_sum(d2);
-    dmx = wave_max(dmx);
-    rmx = wave_max(rmx);
-    if (lane == 0) {
-        sh[0][w] = s;
-        sh[1][w] = s2;
-        sh[2][w] = mx;
-        sh[3][w] = d2;
-        sh[4][w] = dmx;
-        sh[5][w] = rmx;
-    }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        const int q = threadIdx.x;
-        const bool is_max = (q == 2 || q == 4 || q == 5);
-        double acc = sh[q][0];
-        for (int k = 1; k < kReduceThreads / 64; ++k) acc = is_max ? fmax(acc, sh[q][k]) : acc + sh[q][k];
-        part[(int64_t)blockIdx.x * 6 + q] = acc;
+struct Acc6 {
+    double s, s2, mx, d2, dmx, rmx;
+};
+
+__device__ __forceinline__ void acc_add(Acc6 &a, double x, const double *y) {
+    a.s += x;
+    a.s2 += x * x;
+    a.mx = fmax(a.mx, fabs(x));
+    if (y) {
+        const double d = x - *y;
+        a.d2 += d * d;
+        a.dmx = fmax(a.dmx, fabs(d));
+        a.rmx = fmax(a.rmx, fabs(*y));
     }
 }
 
-__global__ void __launch_bounds__(64) reduce_final(const double *__restrict__ part, int nb, double *out) {
-    // one wave: lane q < 6 folds column q over the blocks in block order
-    const int q = threadIdx.x;
-    if (q < 6) {
-        const bool is_max = (q == 2 || q == 4 || q == 5);
-        double acc = part[q];
-        for (int b = 1; b < nb; ++b) {
-            const double v = part[(int64_t)b * 6 + q];
-            acc = is_max ? fmax(acc, v) : acc + v;
+// block-wide fold of the six values in a fixed order; result valid in thread 0
+__device__ __forceinline__ Acc6 block_fold(Acc6 a) {
+    __shared__ double sh[6][kReduceThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    a.s = wave_sum(a.s);
+    a.s2 = wave_sum(a.s2);
+    a.mx = wave_max(a.mx);
+    a.d2 = wave_sum(a.d2);
+    a.dmx = wave_max(a.dmx);
+    a.rmx = wave_max(a.rmx);
+    if (lane == 0) {
+        sh[0][w] = a.s;
+        sh[1][w] = a.s2;
+        sh[2][w] = a.mx;
+        sh[3][w] = a.d2;
+        sh[4][w] = a.dmx;
+        sh[5][w] = a.rmx;
+    }
+    __syncthreads();
+    Acc6 r{sh[0][0], sh[1][0], sh[2][0], sh[3][0], sh[4][0], sh[5][0]};
+    for (int k = 1; k < kReduceThreads / 64; ++k) {
+        r.s += sh[0][k];
+        r.s2 += sh[1][k];
+        r.mx = fmax(r.mx, sh[2][k]);
+        r.d2 += sh[3][k];
+        r.dmx = fmax(r.dmx, sh[4][k]);
+        r.rmx = fmax(r.rmx, sh[5][k]);
+    }
+    return r;
+}
+
+// Each thread folds groups of G consecutive elements, grid-stride; the launch
+// shape depends only on n, so the summation order is fixed for a given n
+// (G = 4 when both pointers allow vector loads, else 1).
+template <typename S, int G>
+__global__ void __launch_bounds__(kReduceThreads)
+    reduce_partials(const S *__restrict__ u, const S *__restrict__ ref, int64_t n, double *part) {
+    Acc6 a{0, 0, 0, 0, 0, 0};
+    const int64_t ngroups = n / G;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += stride) {
+        const VecS<S, G> tu = *reinterpret_cast<const VecS<S, G> *>(u + G * g);
+        if (ref) {
+            const VecS<S, G> tr = *reinterpret_cast<const VecS<S, G> *>(ref + G * g);
+#pragma unroll
+            for (int v = 0; v < G; ++v) {
+                const double y = (double)to_compute(tr.v[v]);
+                acc_add(a, (double)to_compute(tu.v[v]), &y);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < G; ++v) acc_add(a, (double)to_compute(tu.v[v]), nullptr);
         }
-        out[q] = acc;
+    }
+    // tail of n mod G elements: block 0
+    if (blockIdx.x == 0 && threadIdx.x < (int)(n - G * ngroups)) {
+        const int64_t i = G * ngroups + threadIdx.x;
+        const double y = ref ? (double)to_compute(ref[i]) : 0.0;
+        acc_add(a, (double)to_compute(u[i]), ref ? &y : nullptr);
+    }
+    const Acc6 r = block_fold(a);
+    if (threadIdx.x == 0) {
+        double *p = part + (int64_t)blockIdx.x * 6;
+        p[0] = r.s;
+        p[1] = r.s2;
+        p[2] = r.mx;
+        p[3] = r.d2;
+        p[4] = r.dmx;
+        p[5] = r.rmx;
+    }
+}
+
+__global__ void __launch_bounds__(kReduceThreads) reduce_final(const double *__restrict__ part, int nb, double *out) {
+    Acc6 a{0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += kReduceThreads) {
+        const double *p = part + (int64_t)b * 6;
+        a.s += p[0];
+        a.s2 += p[1];
+        a.mx = fmax(a.mx, p[2]);
+        a.d2 += p[3];
+        a.dmx = fmax(a.dmx, p[4]);
+        a.rmx = fmax(a.rmx, p[5]);
+    }
+    const Acc6 r = block_fold(a);
+    if (threadIdx.x == 0) {
+        out[0] = r.s;
+        out[1] = r.s2;
+        out[2] = r.mx;
+        out[3] = r.d2;
+        out[4] = r.dmx;
+        out[5] = r.rmx;
     }
 }
 
 template <typename S>
 static hipError_t launch_reduce_t(const void *u, const void *ref, int64_t n, double *part, double *out,
                                   hipStream_t st) {
-    hipLaunchKernelGGL(reduce_partials<S>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
-                       static_cast<const S *>(u), static_cast<const S *>(ref), n, part);
-    hipLaunchKernelGGL(reduce_final, dim3(1), dim3(64), 0, st, (const double *)part, kReduceBlocks, out);
+    // enough workgroups to stream at full bandwidth, fewer for small n
+    int64_t nb = (n / 4 + kReduceThreads * 8 - 1) / (kReduceThreads * 8);
+    if (nb < 1) nb = 1;
+    if (nb > kReduceBlocks) nb = kReduceBlocks;
+    const uintptr_t al = 4 * sizeof(S);
+    if ((uintptr_t)u % al == 0 && (uintptr_t)ref % al == 0)
+        hipLaunchKernelGGL((reduce_partials<S, 4>), dim3((unsigned)nb), dim3(kReduceThreads), 0, st,
+                           static_cast<const S *>(u), static_cast<const S *>(ref), n, part);
+    else
+        hipLaunchKernelGGL((reduce_partials<S, 1>), dim3((unsigned)nb), dim3(kReduceThreads), 0, st,
+                           static_cast<const S *>(u), static_cast<const S *>(ref), n, part);
+    hipLaunchKernelGGL(reduce_final, dim3(1), dim3(kReduceThreads), 0, st, (const double *)part, (int)nb, out);
     return hipGetLastError();
 }
 

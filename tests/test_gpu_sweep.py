@@ -203,3 +203,13 @@ def test_fp64_reductions(dt):
         assert (got1[3:] == 0).all()
         # deterministic
         assert np.array_equal(reduce(a, b).cpu().numpy(), got)
+
+
+def test_fp64_reductions_unaligned():
+    rng = np.random.default_rng(10)
+    n = 10007
+    base = torch.from_numpy(rng.uniform(-1, 1, n + 1)).float().cuda()
+    a = base[1:]
+    got = reduce(a).cpu().numpy()
+    x = a.double().cpu().numpy()
+    np.testing.assert_allclose(got[:3], [x.sum(), (x * x).sum(), np.abs(x).max()], rtol=1e-12)
