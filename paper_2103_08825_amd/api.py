@@ -86,6 +86,17 @@ class Plan:
         _lib.stencil_run(self.handle, u0.data_ptr(), out.data_ptr(), int(T), _stream())
         return out
 
+    def adjoint(self, u0: torch.Tensor, gT: torch.Tensor, T: int, ckpt: int = 10):
+        """(dL/du0, dL/dc) of u_T = run(u0, T) for dL/du_T = gT.  dL/dc is FP64, one
+        entry per coefficient in canonical order."""
+        _check_tensor(u0, self.dtype, self.numel, "u0")
+        _check_tensor(gT, self.dtype, self.numel, "gT")
+        grad_u0 = torch.empty(self.shape, dtype=self.dtype, device=u0.device)
+        grad_c = torch.empty(len(self.coeffs), dtype=torch.float64, device=u0.device)
+        _lib.stencil_adjoint(self.handle, u0.data_ptr(), gT.data_ptr(), int(T), int(ckpt),
+                             grad_u0.data_ptr(), grad_c.data_ptr(), _stream())
+        return grad_u0, grad_c
+
     def close(self) -> None:
         if getattr(self, "handle", None):
             _lib.stencil_plan_destroy(self.handle)

@@ -1,6 +1,222 @@
-// adjoint.hip -- placeholder until the adjoint sweep lands.
+// adjoint.hip -- reverse-mode derivative of T stencil steps (stencil_adjoint).
+//
+// With lambda_T = dL/du_T, one backward step is
+//     lambda_t[z] = sum_j c_j g(lambda_{t+1}, z - o_j)       (mirrored stencil)
+//     dL/dc_j   += sum_x lambda_{t+1}[x] g(u_t, x + o_j)
+// and dL/du_0 = lambda_0.  The mirrored stencil is the plan's own stencil with
+// the weight of offset o moved to -o, run by the same sweep kernels.  Forward
+// states come from checkpoints every `ckpt` steps (the fused sweep) and are
+// rebuilt one step at a time per segment.  The coefficient sums run in a
+// grid-stride kernel whose workgroups each keep their own FP64 partial slots
+// across all steps (fixed order, no atomics); one fold at the end.
+#include <vector>
+
+#include "device_common.hpp"
 #include "plan.hpp"
+#include "registry.hpp"
+
+namespace stn {
+
+constexpr int kGradBlocks = 1024;
+constexpr int kGradThreads = 256;
+constexpr int kGradMaxP = 32;  // offsets per pass of the gradient kernel
+
+template <typename S>
+__global__ void __launch_bounds__(kGradThreads)
+    coeff_grad_kernel(const S *__restrict__ lam, const S *__restrict__ u, int64_t n0, int64_t n1, int64_t n2,
+                      int bc, const int *__restrict__ off, int j0, int nj, int npts, double *__restrict__ part) {
+    double acc[kGradMaxP];
+#pragma unroll
+    for (int q = 0; q < kGradMaxP; ++q) acc[q] = 0.0;
+    const int64_t total = n0 * n1 * n2;
+    const bool periodic = bc == 1;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x2 = p % n2, x1 = (p / n2) % n1, x0 = p / (n1 * n2);
+        const double l = (double)to_compute(lam[p]);
+#pragma unroll
+        for (int q = 0; q < kGradMaxP; ++q) {
+            if (q < nj) {
+                const int j = j0 + q;
+                int64_t y0 = x0 + off[3 * j], y1 = x1 + off[3 * j + 1], y2 = x2 + off[3 * j + 2];
+                const bool inside = (y0 >= 0 && y0 < n0) && (y1 >= 0 && y1 < n1) && (y2 >= 0 && y2 < n2);
+                double v = 0.0;
+                if (inside) {
+                    v = (double)to_compute(u[(y0 * n1 + y1) * n2 + y2]);
+                } else if (periodic) {
+                    y0 = wrap_index(y0, n0);
+                    y1 = wrap_index(y1, n1);
+                    y2 = wrap_index(y2, n2);
+                    v = (double)to_compute(u[(y0 * n1 + y1) * n2 + y2]);
+                }
+                acc[q] = fma(l, v, acc[q]);
+            }
+        }
+    }
+    // fold the block in a fixed order and add to this block's own slots
+    __shared__ double sh[kGradThreads / 64][kGradMaxP];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kGradMaxP; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) sh[w][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nj) {
+        double v = sh[0][threadIdx.x];
+        for (int k = 1; k < kGradThreads / 64; ++k) v += sh[k][threadIdx.x];
+        part[(int64_t)blockIdx.x * npts + j0 + threadIdx.x] += v;
+    }
+}
+
+// out[j] = sum over blocks of part[block][j], one workgroup per j, fixed order
+__global__ void __launch_bounds__(256) coeff_grad_fold(const double *__restrict__ part, int nb, int npts,
+                                                       double *__restrict__ out) {
+    const int j = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) v += part[(int64_t)b * npts + j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out[j] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+__global__ void fill_zero_f64(double *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+template <typename S>
+static hipError_t launch_grad(const stencil_plan *p, const void *lam, const void *u, const int *d_off, double *part,
+                              hipStream_t st) {
+    for (int j0 = 0; j0 < p->npts; j0 += kGradMaxP) {
+        const int nj = p->npts - j0 < kGradMaxP ? p->npts - j0 : kGradMaxP;
+        hipLaunchKernelGGL(coeff_grad_kernel<S>, dim3(kGradBlocks), dim3(kGradThreads), 0, st,
+                           static_cast<const S *>(lam), static_cast<const S *>(u), p->n0, p->n1, p->n2, p->bc,
+                           d_off, j0, nj, p->npts, part);
+    }
+    return hipGetLastError();
+}
+
+// one step of the stencil (weights `dense`, generic tables d_off/d_coef) from src to dst
+static int one_step(stencil_plan *p, const Exec &ex, const std::vector<double> &dense, const int *d_off,
+                    const void *d_coef, const void *src, void *dst, hipStream_t st) {
+    const SweepLauncher fn = ex.method == STENCIL_METHOD_GENERIC ? nullptr : pass_launcher(p, ex, 1);
+    if (fn) {
+        SweepLaunch L{src, dst, p->n0, p->n1, p->n2, p->bc, dense.data(), ex.chunk};
+        const hipError_t e = fn(L, st);
+        if (e != hipSuccess) return fail(STENCIL_E_DEVICE, "adjoint sweep launch: %s", hipGetErrorString(e));
+        return STENCIL_OK;
+    }
+    const hipError_t e = launch_generic(p->dtype, src, dst, p->n0, p->n1, p->n2, p->npts, p->bc, d_off, d_coef, st);
+    if (e != hipSuccess) return fail(STENCIL_E_DEVICE, "adjoint generic launch: %s", hipGetErrorString(e));
+    return STENCIL_OK;
+}
+
+static int adjoint_impl(stencil_plan *p, const Exec &ex, const void *d_u0, const void *d_gT, int64_t T,
+                        int64_t C, void *d_gu, double *d_gc, hipStream_t st) {
+    const size_t field = (size_t)p->points * elem_bytes(p->dtype);
+    if (T == 0) {
+        if (d_gu != d_gT) STN_HIP(hipMemcpyAsync(d_gu, d_gT, field, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(fill_zero_f64, dim3(1), dim3(64), 0, st, d_gc, (int64_t)p->npts);
+        STN_HIP(hipGetLastError());
+        return STENCIL_OK;
+    }
+    const int64_t nseg = (T + C - 1) / C;
+    const int64_t seglen = T < C ? T : C;
+    // mirrored weights: offset o takes the weight of -o (the dense table reversed)
+    std::vector<double> dense_m(p->dense.rbegin(), p->dense.rend());
+    // mirrored generic tables (offsets negated, weights unchanged)
+    std::vector<int> off3(3 * p->npts, 0), off3m(3 * p->npts, 0);
+    static const int view_axis[4][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 1, 2}};
+    for (int j = 0; j < p->npts; ++j)
+        for (int i = 0; i < p->dim; ++i) {
+            off3[3 * j + view_axis[p->dim][i]] = p->offsets[j * p->dim + i];
+            off3m[3 * j + view_axis[p->dim][i]] = -p->offsets[j * p->dim + i];
+        }
+    // workspace (stream ordered): checkpoints 1..nseg-1, segment states 1..seglen-1,
+    // two adjoint fields, partial sums, offset tables
+    const int64_t nck = nseg - 1, nst = seglen - 1;
+    const size_t part_bytes = (size_t)kGradBlocks * p->npts * sizeof(double);
+    const size_t tab_bytes = 2 * off3.size() * sizeof(int);
+    const size_t ws_bytes = (size_t)(nck + nst + 2) * field + part_bytes + tab_bytes + 256;
+    char *ws = nullptr;
+    STN_HIP(hipMallocAsync((void **)&ws, ws_bytes, st));
+    auto ck = [&](int64_t s) -> void * { return s == 0 ? const_cast<void *>(d_u0) : ws + (size_t)(s - 1) * field; };
+    char *seg_base = ws + (size_t)nck * field;
+    char *lam_buf[2] = {ws + (size_t)(nck + nst) * field, ws + (size_t)(nck + nst + 1) * field};
+    double *part = reinterpret_cast<double *>(ws + (size_t)(nck + nst + 2) * field);
+    int *d_off = reinterpret_cast<int *>(reinterpret_cast<char *>(part) + part_bytes);
+    int *d_offm = d_off + off3.size();
+    int rc = STENCIL_OK;
+    auto done = [&](int code) {
+        (void)hipFreeAsync(ws, st);
+        return code;
+    };
+    hipError_t e = hipMemcpyAsync(d_off, off3.data(), off3.size() * sizeof(int), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_offm, off3m.data(), off3m.size() * sizeof(int), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return done(fail(STENCIL_E_DEVICE, "adjoint table upload: %s", hipGetErrorString(e)));
+    hipLaunchKernelGGL(fill_zero_f64, dim3(256), dim3(256), 0, st, part, (int64_t)kGradBlocks * p->npts);
+
+    // forward: checkpoints u_{s C}
+    for (int64_t s = 1; s < nseg && rc == STENCIL_OK; ++s) rc = run_passes(p, ex, ck(s - 1), ck(s), C, st);
+    if (rc != STENCIL_OK) return done(rc);
+
+    const void *lam = d_gT;
+    int flip = 0;
+    for (int64_t s = nseg - 1; s >= 0; --s) {
+        const int64_t tb = s * C, te = (tb + C < T) ? tb + C : T;
+        auto state = [&](int64_t t) -> const void * {
+            return t == tb ? ck(s) : static_cast<const void *>(seg_base + (size_t)(t - tb - 1) * field);
+        };
+        for (int64_t t = tb + 1; t < te && rc == STENCIL_OK; ++t)
+            rc = one_step(p, ex, p->dense, p->d_off, p->d_coef, state(t - 1), const_cast<void *>(state(t)), st);
+        if (rc != STENCIL_OK) return done(rc);
+        for (int64_t t = te - 1; t >= tb; --t) {
+            e = p->dtype == STENCIL_F64 ? launch_grad<double>(p, lam, state(t), d_off, part, st)
+                                        : launch_grad<float>(p, lam, state(t), d_off, part, st);
+            if (e != hipSuccess) return done(fail(STENCIL_E_DEVICE, "gradient launch: %s", hipGetErrorString(e)));
+            void *out = (t == 0) ? d_gu : lam_buf[flip];
+            // the generic fallback needs mirrored weights in compute precision on the device:
+            // the plan's d_coef holds the weights in canonical order, which pair with d_offm
+            rc = one_step(p, ex, dense_m, d_offm, p->d_coef, lam, out, st);
+            if (rc != STENCIL_OK) return done(rc);
+            lam = out;
+            flip ^= 1;
+        }
+    }
+    hipLaunchKernelGGL(coeff_grad_fold, dim3(p->npts), dim3(256), 0, st, (const double *)part, kGradBlocks, p->npts,
+                       d_gc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return done(fail(STENCIL_E_DEVICE, "gradient fold: %s", hipGetErrorString(e)));
+    return done(STENCIL_OK);
+}
+
+}  // namespace stn
+
 using namespace stn;
-extern "C" int stencil_adjoint(stencil_plan *, const void *, const void *, int64_t, int64_t, void *, double *, void *) {
-    return fail(STENCIL_E_UNSUPPORTED, "adjoint is not built yet");
+
+extern "C" int stencil_adjoint(stencil_plan *p, const void *d_u0, const void *d_gT, int64_t T,
+                               int64_t checkpoint_every, void *d_grad_u0, double *d_grad_coeffs, void *stream) {
+    clear_error();
+    if (!p) return fail(STENCIL_E_INVALID, "plan is NULL");
+    if (!d_u0 || !d_gT || !d_grad_u0 || !d_grad_coeffs) return fail(STENCIL_E_INVALID, "NULL pointer");
+    if (T < 0) return fail(STENCIL_E_INVALID, "T must be >= 0");
+    if (checkpoint_every < 1) return fail(STENCIL_E_INVALID, "checkpoint_every must be >= 1");
+    if (p->dtype != STENCIL_F64 && p->dtype != STENCIL_F32)
+        return fail(STENCIL_E_UNSUPPORTED, "the adjoint supports FP64 and FP32 plans");
+    if (d_grad_u0 == d_u0 || (d_grad_u0 == d_gT && T > 0))
+        return fail(STENCIL_E_INVALID, "d_grad_u0 must not alias d_u0 or d_gT");
+    hipStream_t st = (hipStream_t)stream;
+    const int rc = plan_prepare(p, st);
+    if (rc != STENCIL_OK) return rc;
+    // the workspace is 256-byte aligned; the caller's three buffers decide the lane
+    // width (alignments are powers of two, so OR-ing two addresses keeps the weaker)
+    const void *either = reinterpret_cast<const void *>((uintptr_t)d_u0 | (uintptr_t)d_gT);
+    const Exec ex = exec_for_ptrs(p, either, d_grad_u0);
+    return adjoint_impl(p, ex, d_u0, d_gT, T, checkpoint_every, d_grad_u0, d_grad_coeffs, st);
 }

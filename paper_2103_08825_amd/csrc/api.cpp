@@ -328,7 +328,7 @@ int run_passes(stencil_plan *p, const Exec &ex, const void *src, void *dst, int6
 }
 
 // choose an execution whose lane width suits both pointers
-static Exec exec_for_ptrs(const stencil_plan *p, const void *a, const void *b) {
+Exec exec_for_ptrs(const stencil_plan *p, const void *a, const void *b) {
     Exec ex = p->exec;
     if (ex.method == STENCIL_METHOD_GENERIC || variant_fits_ptr(p, ex.variant, a, b)) return ex;
     for (int v = 1; v <= num_variants_of(p->dim); ++v) {

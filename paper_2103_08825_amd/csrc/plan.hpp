@@ -61,6 +61,8 @@ int plan_prepare(stencil_plan *p, hipStream_t st);
 int plan_alloc_alias(stencil_plan *p);
 // enqueue T steps with an explicit execution choice (no aliasing handling)
 int run_passes(stencil_plan *p, const Exec &ex, const void *src, void *dst, int64_t T, hipStream_t st);
+// ex with a lane width both pointers allow (falls back to the generic kernel)
+Exec exec_for_ptrs(const stencil_plan *p, const void *a, const void *b);
 // launcher of one pass of k steps under ex (nullptr if none)
 SweepLauncher pass_launcher(const stencil_plan *p, const Exec &ex, int k);
 hipError_t launch_reduce(int dtype, const void *u, const void *ref, int64_t n, double *part,

@@ -1,0 +1,135 @@
+"""GPU parity of the adjoint sweep (stencil_adjoint) and the autograd function.
+
+References: the FP64 oracle's checkpointed adjoint (itself pinned to the
+Fourier closed form, the dot-product identity and central differences),
+plus the same identities checked directly on the GPU path.  Tolerances:
+FP64 1e-10, FP32 1e-4 (normwise for dL/du0, relative to max|dL/dc| for dL/dc).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import rel_err, rounded_inputs, say
+from paper_2103_08825_amd import Plan
+from paper_2103_08825_amd import workloads as W
+from paper_2103_08825_amd._lib import StencilError
+from paper_2103_08825_amd.autograd import StencilFn, StencilSpec
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-4}
+SHAPES = {1: (301,), 2: (37, 64), 3: (11, 20, 64)}
+
+
+def _setup(dim, r, kind, bc, dt, seed=0, shape=None):
+    shape = shape or SHAPES[dim]
+    rng = np.random.default_rng(seed)
+    c = W.coefficients(rng, W.num_points(dim, r, kind))
+    u0 = rng.uniform(-1, 1, shape)
+    y = rng.uniform(-1, 1, shape)
+    t_in, u_ex, c_ex = rounded_inputs(u0, c, dt)
+    return shape, c, c_ex, t_in.cuda(), u_ex, y
+
+
+@pytest.mark.parametrize("dim,r,kind", [(1, 1, 0), (1, 2, 0), (2, 1, 0), (2, 1, 1), (2, 2, 1),
+                                        (3, 1, 0), (3, 1, 1), (3, 2, 0)])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_adjoint_matches_oracle(dim, r, kind, bc, dt):
+    shape, c, c_ex, x, u_ex, y = _setup(dim, r, kind, bc, dt, seed=dim + 3 * r + kind)
+    T, ckpt = 9, 4
+    plan = Plan(shape, r, kind, c, bc, dt)
+    say("adjoint dim=%d r=%d kind=%d bc=%d %s plan=%s" % (dim, r, kind, bc, dt, plan.info()["method"]))
+    uT = plan.run(x, T)
+    g = (uT - torch.from_numpy(y).to(uT.dtype).cuda()).contiguous()
+    gu, gc = plan.adjoint(x, g, T, ckpt)
+    torch.cuda.synchronize()
+    ref_u, ref_c = oracle.adjoint(u_ex, c_ex, g.double().cpu().numpy(), T, r=r, kind=kind, bc=bc,
+                                  ckpt=ckpt)
+    e_u = rel_err(gu.double().cpu().numpy(), ref_u)
+    e_c = rel_err(gc.cpu().numpy(), ref_c)
+    assert e_u <= TOL[dt] and e_c <= TOL[dt], (e_u, e_c)
+
+
+def test_adjoint_checkpoint_interval_invariance_bitwise():
+    """The recomputed states and the partial sums do not depend on the interval."""
+    shape, c, c_ex, x, u_ex, y = _setup(3, 1, 0, 0, "f32", seed=4)
+    plan = Plan(shape, 1, 0, c, 0, "f32")
+    g = torch.from_numpy(y).float().cuda()
+    ref_u, ref_c = plan.adjoint(x, g, 13, 1)
+    for ck in (2, 5, 13, 40):
+        gu, gc = plan.adjoint(x, g, 13, ck)
+        torch.cuda.synchronize()
+        assert torch.equal(gu, ref_u) and torch.equal(gc, ref_c), ck
+
+
+@pytest.mark.parametrize("dim,r,kind,bc", [(2, 1, 1, 1), (3, 1, 0, 0), (3, 2, 0, 1), (1, 2, 0, 0)])
+def test_dot_product_identity_gpu(dim, r, kind, bc):
+    """<A u, w> = <u, A^T w> with both sides computed on the GPU (FP64)."""
+    shape, c, c_ex, x, u_ex, y = _setup(dim, r, kind, bc, "f64", seed=20)
+    w = torch.from_numpy(y).cuda()
+    plan = Plan(shape, r, kind, c, bc, "f64")
+    T = 11
+    Au = plan.run(x, T)
+    ATw, _ = plan.adjoint(x, w, T, 3)
+    lhs = float(torch.sum(Au * w))
+    rhs = float(torch.sum(x * ATw))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def test_coefficient_gradient_central_differences_gpu():
+    """L = 0.5 ||u_T - y||^2; dL/dc against central differences of GPU sweeps (FP64)."""
+    dim, r, kind, bc = 3, 1, 0, 1
+    shape, c, c_ex, x, u_ex, y = _setup(dim, r, kind, bc, "f64", seed=21)
+    yt = torch.from_numpy(y).cuda()
+    T = 6
+
+    def loss(cc):
+        p = Plan(shape, r, kind, cc, bc, "f64")
+        v = 0.5 * float(torch.sum((p.run(x, T) - yt) ** 2))
+        p.close()
+        return v
+
+    plan = Plan(shape, r, kind, c, bc, "f64")
+    g = (plan.run(x, T) - yt).contiguous()
+    _, gc = plan.adjoint(x, g, T, 2)
+    gc = gc.cpu().numpy()
+    h = 1e-5
+    for j in range(len(c)):
+        e = np.zeros_like(c)
+        e[j] = h
+        fd = (loss(c + e) - loss(c - e)) / (2 * h)
+        assert abs(fd - gc[j]) <= 1e-6 * max(1.0, abs(gc[j])), (j, fd, gc[j])
+
+
+def test_autograd_function_matches_adjoint():
+    shape, c, c_ex, x, u_ex, y = _setup(3, 1, 0, 1, "f32", seed=22)
+    spec = StencilSpec(shape, 1, 0, 1, "f32")
+    u0 = x.clone().requires_grad_(True)
+    coeffs = torch.tensor(c, dtype=torch.float64, requires_grad=True)
+    yt = torch.from_numpy(y).float().cuda()
+    T = 10
+    uT = StencilFn.apply(u0, coeffs, spec, T, 5)
+    loss = 0.5 * torch.sum((uT - yt) ** 2)
+    loss.backward()
+    plan = Plan(shape, 1, 0, c, 1, "f32")
+    g = (plan.run(x, T) - yt).contiguous()
+    gu, gc = plan.adjoint(x, g, T, 5)
+    torch.cuda.synchronize()
+    assert torch.equal(u0.grad, gu)
+    np.testing.assert_allclose(coeffs.grad.numpy(), gc.cpu().numpy(), rtol=0, atol=0)
+
+
+def test_adjoint_T_zero_and_argument_errors():
+    shape, c, c_ex, x, u_ex, y = _setup(2, 1, 0, 0, "f32", seed=23)
+    plan = Plan(shape, 1, 0, c, 0, "f32")
+    g = torch.from_numpy(y).float().cuda()
+    gu, gc = plan.adjoint(x, g, 0, 10)
+    torch.cuda.synchronize()
+    assert torch.equal(gu, g) and torch.equal(gc, torch.zeros_like(gc))
+    with pytest.raises(StencilError):
+        plan.adjoint(x, g, 5, 0)
+    bf = Plan(shape, 1, 0, c, 0, "bf16")
+    with pytest.raises(StencilError):
+        bf.adjoint(x.bfloat16(), g.bfloat16(), 5, 2)

@@ -213,3 +213,29 @@ def test_fp64_reductions_unaligned():
     got = reduce(a).cpu().numpy()
     x = a.double().cpu().numpy()
     np.testing.assert_allclose(got[:3], [x.sum(), (x * x).sum(), np.abs(x).max()], rtol=1e-12)
+
+
+@pytest.mark.parametrize("dim,r,kind,dt", [(3, 1, 0, "f32"), (3, 1, 1, "f32"), (3, 2, 0, "f64"),
+                                           (2, 1, 1, "f32"), (2, 2, 0, "f32"), (1, 1, 0, "f64"),
+                                           (3, 1, 0, "bf16")])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_fused_plain_generic_bitwise_on_random_inputs(dim, r, kind, dt, bc):
+    """Every kernel accumulates a point's terms in the same order with the same
+    fused multiply-adds, so all methods agree bit for bit on any input -- except
+    that with 16-bit storage a fused pass keeps its intermediate steps in FP32
+    (rounding only on the store), so there only plain and generic coincide."""
+    shape = SHAPES_VX[dim]
+    c, u0 = _case(dim, r, kind, bc, shape, 12)
+    x = torch.from_numpy(u0).to(TORCH[dt]).cuda()
+    outs = {}
+    for method in ("fused", "plain", "generic"):
+        say("bitwise dim=%d r=%d kind=%d %s bc=%d %s" % (dim, r, kind, dt, bc, method))
+        p = Plan(shape, r, kind, c, bc, dt, method=method, chunk=CHUNK[dim])
+        outs[method] = p.run(x, 7)
+        torch.cuda.synchronize()
+    assert torch.equal(outs["plain"], outs["generic"])
+    if dt in ("f32", "f64"):
+        assert torch.equal(outs["fused"], outs["plain"])
+    else:
+        ref = outs["plain"].double()
+        assert float((outs["fused"].double() - ref).abs().max() / ref.abs().max()) <= TOL[dt]
