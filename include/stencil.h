@@ -165,6 +165,10 @@ int stencil_batch_launch(stencil_batch *b, void *stream);
 void stencil_batch_destroy(stencil_batch *b);
 /* Number of work items and of persistent workgroups of a batch. */
 int stencil_batch_info(const stencil_batch *b, int64_t *items, int64_t *workgroups);
+/* Synchronises `stream` and reports whether the last replay completed every
+ * work item: STENCIL_E_DEVICE if a work item gave up waiting for its
+ * predecessor (a bounded wait; it cannot happen with a well-formed list). */
+int stencil_batch_status(const stencil_batch *b, void *stream);
 
 /* --- derivative --------------------------------------------------------------- */
 

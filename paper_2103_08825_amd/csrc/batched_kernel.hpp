@@ -1,0 +1,163 @@
+// batched_kernel.hpp -- the persistent kernel of the batched sweep (see batched.hip).
+#pragma once
+
+#include "stream_kernel.hpp"
+
+namespace stn {
+
+// the persistent kernel's tile shape: one column per lane (any width), 4 waves
+constexpr int kBatchVX = 1;
+constexpr int kBatchNW = 4;
+constexpr int kBatchMaxK1 = 8;  // fused steps compiled for order-1 stencils
+constexpr int kBatchMaxK2 = 4;  // ... for order-2 stencils
+constexpr int kBatchChunk = 128;
+// A wait gives up after this many ticks of the 100 MHz real-time counter
+// (about one second), or at once when another workgroup already gave up.
+constexpr uint64_t kWaitTicks = 100000000ull;
+
+struct BatchGrid {
+    const void *in;
+    void *out;
+    void *scratch;
+    int64_t n0, n2;
+    int r, box, bc, npass, k, krem, nblk;
+    int tiles_x, chunk, chunks, out_x, halo_x;
+    double coef[25];  // dense [dz][dx], (2r+1)^2 <= 25
+};
+
+struct BatchItem {
+    int grid, pass, blk, pad;
+};
+
+struct BatchArgs {
+    const BatchGrid *grids;
+    const BatchItem *items;
+    int64_t nitems;
+    int *counters;  // one per grid
+    int *cursor;
+    int *error;
+};
+
+__device__ __forceinline__ const void *pass_src(const BatchGrid &g, int p) {
+    if (p == 0) return g.in;
+    return ((g.npass - p) % 2 == 0) ? g.out : g.scratch;
+}
+__device__ __forceinline__ void *pass_dst(const BatchGrid &g, int p) {
+    return ((g.npass - (p + 1)) % 2 == 0) ? g.out : g.scratch;
+}
+
+template <typename S, int R, bool BOX, int K>
+__device__ __forceinline__ void run_item(const BatchGrid &g, int pass, int blk) {
+    using C = typename ComputeOf<S>::type;
+    StreamArgs<C> a;
+    a.src = pass_src(g, pass);
+    a.dst = pass_dst(g, pass);
+    a.n0 = g.n0;
+    a.n1 = 1;
+    a.n2 = g.n2;
+    a.tiles_x = g.tiles_x;
+    a.tiles_y = 1;
+    a.chunks = g.chunks;
+    a.chunk = g.chunk;
+    a.out_x = g.out_x;
+    a.out_y = 1;
+    a.halo_x = g.halo_x;
+    a.bc = g.bc;
+    a.nblocks = g.nblk;
+    constexpr int W = 2 * R + 1;
+#pragma unroll
+    for (int i = 0; i < W * W; ++i) a.coef[i] = (C)g.coef[i];
+    stream_tile<S, 2, R, BOX, K, kBatchVX, kBatchNW, 1>(a, blk);
+}
+
+template <typename S, int R, bool BOX, int KMAX>
+__device__ __forceinline__ void dispatch_k(const BatchGrid &g, int pass, int blk, int k) {
+    static_for<1, KMAX + 1>([&](auto K_) {
+        constexpr int K = decltype(K_)::value;
+        if (k == K) run_item<S, R, BOX, K>(g, pass, blk);
+    });
+}
+
+template <typename S>
+__global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs a) {
+    __shared__ int item_sh;
+    __shared__ int ok_sh;
+    // Lane 0 of the workgroup does all bookkeeping in one place, between the
+    // two barriers that open an iteration: it counts the item finished in the
+    // previous iteration, then takes the next one.  Loop control is read back
+    // with readfirstlane, so the loop is uniform for the compiler as well: two
+    // separate lane-0 regions around the back-edge (count at the end, take at
+    // the top) can otherwise be merged into a loop of their own that lane 0
+    // enters only after the rest of its wave has left -- which it never does.
+    int done_grid = -1;  // grid of the item finished in the previous iteration
+    for (;;) {
+        __syncthreads();  // the previous item is fully processed and fenced
+        if (threadIdx.x == 0) {
+            if (done_grid >= 0)
+                __hip_atomic_fetch_add(a.counters + done_grid, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            item_sh = atomicAdd(a.cursor, 1);
+        }
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(item_sh);
+        if (it >= a.nitems) break;  // scalar branch: every wave leaves together
+        const int grid = __builtin_amdgcn_readfirstlane(a.items[it].grid);
+        const int ipass = __builtin_amdgcn_readfirstlane(a.items[it].pass);
+        const int iblk = __builtin_amdgcn_readfirstlane(a.items[it].blk);
+        const BatchGrid &g = a.grids[grid];
+        if (threadIdx.x == 0) {
+            int ok = 1;
+            if (ipass > 0) {
+                // poll with relaxed device-coherent loads; a single acquire follows
+                const int need = ipass * g.nblk;
+                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                while (__hip_atomic_load(a.counters + grid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                        __builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
+                        ok = 0;
+                        __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+            }
+            ok_sh = ok;
+        }
+        __syncthreads();
+        // every wave sees the previous pass's stores (other XCDs' L2s included)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int ok = __builtin_amdgcn_readfirstlane(ok_sh);
+        if (ok) {
+            const int npass = __builtin_amdgcn_readfirstlane(g.npass);
+            const int krem = __builtin_amdgcn_readfirstlane(g.krem);
+            const int k = ipass < npass - 1 || krem == 0 ? __builtin_amdgcn_readfirstlane(g.k) : krem;
+            const int r = __builtin_amdgcn_readfirstlane(g.r);
+            const int box = __builtin_amdgcn_readfirstlane(g.box);
+            if (r == 1) {
+                if (box)
+                    dispatch_k<S, 1, true, kBatchMaxK1>(g, ipass, iblk, k);
+                else
+                    dispatch_k<S, 1, false, kBatchMaxK1>(g, ipass, iblk, k);
+            } else {
+                if (box)
+                    dispatch_k<S, 2, true, kBatchMaxK2>(g, ipass, iblk, k);
+                else
+                    dispatch_k<S, 2, false, kBatchMaxK2>(g, ipass, iblk, k);
+            }
+        }
+        // publish this block's stores; lane 0 counts the item after the next barrier
+        __threadfence();
+        done_grid = grid;
+    }
+}
+
+// launchers and occupancy queries, one per storage type (batched_<dtype>.hip)
+hipError_t launch_batched_f64(const BatchArgs &a, int wgs, hipStream_t st);
+hipError_t launch_batched_f32(const BatchArgs &a, int wgs, hipStream_t st);
+hipError_t launch_batched_bf16(const BatchArgs &a, int wgs, hipStream_t st);
+hipError_t launch_batched_f16(const BatchArgs &a, int wgs, hipStream_t st);
+const void *batched_kernel_f64();
+const void *batched_kernel_f32();
+const void *batched_kernel_bf16();
+const void *batched_kernel_f16();
+
+}  // namespace stn

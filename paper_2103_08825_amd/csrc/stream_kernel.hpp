@@ -58,9 +58,11 @@ template <int DX, int V, int VX, typename C> __device__ __forceinline__ C xval(c
     return lane_shift<s>(row[m]);
 }
 
+// One workgroup's share of a fused launch: logical block `blk` of the grid
+// described by `a`.  Called by stream_kernel (one block per workgroup) and by
+// the persistent batched kernel (one block per work item).
 template <typename S, int DIM, int R, bool BOX, int K, int VX, int NW, int RW>
-__global__ void __launch_bounds__(64 * NW)
-    stream_kernel(const StreamArgs<typename ComputeOf<S>::type> a) {
+__device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<S>::type> &a, const int blk) {
     using C = typename ComputeOf<S>::type;
     constexpr int W = 2 * R + 1;
     constexpr int EXT = (DIM == 3) ? RW + 2 * R : 1;
@@ -76,7 +78,6 @@ __global__ void __launch_bounds__(64 * NW)
     const bool periodic = (a.bc == 1);
 
     // ---- which tile ---------------------------------------------------------
-    const int blk = xcd_remap(blockIdx.x, a.nblocks);
     int tx, ty, zc;
     if constexpr (DIM == 3) {
         tx = blk % a.tiles_x;
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(64 * NW)
         tx = (blk % groups) * NW + wv;
         zc = blk / groups;
         ty = 0;
-        if (tx >= a.tiles_x) return;  // 2D waves are independent: no barrier below
+        if (tx >= a.tiles_x) return;  // 2D waves are independent: no barrier inside
     }
     const int64_t n0 = a.n0, n1 = a.n1, n2 = a.n2;
     const int64_t plane = n1 * n2;
@@ -158,7 +159,8 @@ __global__ void __launch_bounds__(64 * NW)
     constexpr int kHaloLevels = XCH ? K : 1;
     constexpr int kHaloWaves = XCH ? NW : 1;
     constexpr int kHaloRows = XCH ? R : 1;
-    __shared__ C halo[2][kHaloLevels][kHaloWaves][2][kHaloRows][64 * VX];
+    constexpr int kHaloLanes = XCH ? 64 * VX : 1;
+    __shared__ C halo[2][kHaloLevels][kHaloWaves][2][kHaloRows][kHaloLanes];
 
     // next plane to fetch: stream index, (wrapped) grid plane and its base
     int ld_s = 0;
@@ -338,6 +340,12 @@ __global__ void __launch_bounds__(64 * NW)
             if (s < nsteps) step(PH_, s);
         });
     }
+}
+
+template <typename S, int DIM, int R, bool BOX, int K, int VX, int NW, int RW>
+__global__ void __launch_bounds__(64 * NW)
+    stream_kernel(const StreamArgs<typename ComputeOf<S>::type> a) {
+    stream_tile<S, DIM, R, BOX, K, VX, NW, RW>(a, xcd_remap(blockIdx.x, a.nblocks));
 }
 
 }  // namespace stn
