@@ -240,6 +240,16 @@ def main(argv=None):
             "kernel": "stream_kernel<float,3,R=1,star,K=%d> variant %d" % (k, info["variant"]),
             "launch_ms": launch_ms}
 
+    # the same kernel seen from the vector ALU: useful FMAs (7 per point-step, k steps
+    # per launch) against the FP32 vector peak without packed math (256 CU x 64 lanes
+    # x 2 FLOP x 2.4 GHz = 78.6 TFLOP/s; the build keeps packed FP32 off)
+    useful_flops = 2.0 * case.npts * k * points
+    roof_alu = {"bound": "alu", "achieved": useful_flops / (launch_ms * 1e-3) / 1e12, "peak": 78.6,
+                "unit": "TFLOP/s",
+                "frac": useful_flops / (launch_ms * 1e-3) / 1e12 / 78.6,
+                "note": "useful FMAs only; the recomputed tile halo and the chunk fill add "
+                        "issued VALU work (see profiles/stream3d_7p_512_f32_sq_counters.md)"}
+
     cpu = None
     if not a.no_cpu_baseline:
         log("cpu baseline ...")
@@ -258,7 +268,7 @@ def main(argv=None):
         "sweep_ms_per_step": ms_sweep, "wall_ms_per_step": wall,
         "plain": plain_rec,
         "speedup_vs_plain": (plain_rec["ms_per_step"] / ms) if plain_rec else None,
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "roofline_alu": roof_alu, "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
     fused.close()

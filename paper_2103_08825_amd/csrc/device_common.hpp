@@ -89,8 +89,16 @@ using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int kBufferFlags = 0x00020000;  // raw 32-bit dword access (gfx9 family)
 constexpr uint32_t kOutOfRange = 0x80000000u;  // byte offset beyond every resource
 
+// The descriptor must live in scalar registers; its fields are uniform by
+// construction, and readfirstlane says so to the compiler (a descriptor built
+// from vector registers forces a loop over distinct values around every access).
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufferFlags);
+    const uint64_t p = (uint64_t)base;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)p);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(p >> 32));
+    const int n = __builtin_amdgcn_readfirstlane((int)bytes);
+    void *q = (void *)(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, n, kBufferFlags);
 }
 
 template <int BYTES> struct BufWord;

@@ -129,11 +129,6 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
         ld_off[i] = (y_ok && x_in) ? off : kOutOfRange;
         st_off[i] = (y_st && x_out) ? off : kOutOfRange;
     }
-    // widened tile entirely inside the grid in x and y: no per-point masking
-    const bool interior =
-        (x_base >= 0) && (x_base + 64 * VX <= n2) &&
-        (DIM == 2 || ((y_base >= 0) && (y_base + NW * RW <= n1)));
-    const bool mask_points = !periodic && !interior;
     const uint32_t plane_bytes = (uint32_t)(plane * (int64_t)sizeof(S));
 
     // ---- z chunk (the streamed extent is below 2^31, checked on the host) -------
@@ -143,6 +138,13 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
     const int zs = z_out0 - K * R;  // plane loaded at step 0
     const int nload = (z_out1 - z_out0) + 2 * K * R;
     const int nsteps = (z_out1 - z_out0) + K * W;
+    // Zero halo: a completed level plane must read 0 outside the grid.  If the
+    // widened tile and every plane the chunk's outputs depend on lie inside the
+    // grid, nothing needs masking (the common case); otherwise each completed
+    // plane is masked with one select per point.
+    const bool inside_xy = (x_base >= 0) && (x_base + 64 * VX <= n2) &&
+                           (DIM == 2 || ((y_base >= 0) && (y_base + NW * RW <= n1)));
+    const bool no_mask = periodic || (inside_xy && zs >= 0 && z_out1 + K * R <= nz);
 
     // ---- state ------------------------------------------------------------------
     C acc[K][W][RW][VX];  // level j+1's ring of pending output planes
@@ -197,8 +199,9 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
     };
 
     // one step of the stream; PH = s mod W selects ring slots at compile time
-    auto step = [&](auto PH_, int s) {
+    auto step = [&](auto PH_, auto MASK_, int s) {
         constexpr int PH = decltype(PH_)::value;
+        constexpr bool MASK = decltype(MASK_)::value;
         const int rd = (s + 1) & 1;  // LDS slot written by the previous step
         const int wr = s & 1;
 
@@ -275,22 +278,15 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
                 }
             });
             // plane m-R of level j is complete: apply the zero halo
-            if constexpr (j < K) {
-                if (!periodic) {
-                    constexpr int cslot = posmod(PH - j * (R + 1), W);
-                    const int z = zs + s - j * (R + 1);
-                    if (z < 0 || z >= nz) {
+            if constexpr (j < K && MASK) {
+                constexpr int cslot = posmod(PH - j * (R + 1), W);
+                const int z = zs + s - j * (R + 1);
+                const bool z_ok = (z >= 0) && (z < nz);
 #pragma unroll
-                        for (int i = 0; i < RW; ++i)
+                for (int i = 0; i < RW; ++i) {
+                    const bool keep = z_ok && y_in[i] && x_in;
 #pragma unroll
-                            for (int v = 0; v < VX; ++v) acc[j - 1][cslot][i][v] = C(0);
-                    } else if (mask_points) {
-#pragma unroll
-                        for (int i = 0; i < RW; ++i)
-#pragma unroll
-                            for (int v = 0; v < VX; ++v)
-                                if (!(y_in[i] && x_in)) acc[j - 1][cslot][i][v] = C(0);
-                    }
+                    for (int v = 0; v < VX; ++v) acc[j - 1][cslot][i][v] = keep ? acc[j - 1][cslot][i][v] : C(0);
                 }
             }
         });
@@ -334,12 +330,18 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
     for (int i = 0; i < RW; ++i)
 #pragma unroll
         for (int v = 0; v < VX; ++v) pf[W - 1][i][v] = C(0);
-    for (int s0 = 0; s0 < nsteps; s0 += W) {
-        static_for<0, W>([&](auto PH_) {
-            const int s = s0 + decltype(PH_)::value;
-            if (s < nsteps) step(PH_, s);
-        });
-    }
+    auto run = [&](auto MASK_) {
+        for (int s0 = 0; s0 < nsteps; s0 += W) {
+            static_for<0, W>([&](auto PH_) {
+                const int s = s0 + decltype(PH_)::value;
+                if (s < nsteps) step(PH_, MASK_, s);
+            });
+        }
+    };
+    if (no_mask)
+        run(std::integral_constant<bool, false>{});
+    else
+        run(std::integral_constant<bool, true>{});
 }
 
 template <typename S, int DIM, int R, bool BOX, int K, int VX, int NW, int RW>
