@@ -88,7 +88,7 @@ def cpu_baseline(u0_f64, coeffs, r, kind, bc, budget_s=12.0):
 def bench_batched(a):
     """256 independent 2D FP32 grids (sides log-uniform in [64, 2048], 5-point star
     or 9-point box, T uniform in [10, 200], zero halo): one graph-captured
-    persistent launch (per-grid k autotuned) against 256 separate plain sweeps
+    persistent launch (library default depth and chunk) against 256 separate plain sweeps
     (k = 1, one launch per step) and 256 separate fused sweeps."""
     import torch
     from paper_2103_08825_amd import Plan, workloads as W
@@ -114,8 +114,8 @@ def bench_batched(a):
 
     fused = [Plan(g.shape, 1, g.kind, g.coeffs, W.BC_ZERO, "f32") for g in grids]
     t0 = time.time()
-    batch = Batch(fused, xs, ys, Ts, autotune=True)
-    log("batch build + per-grid autotune %.1fs, items/workgroups %s" % (time.time() - t0, batch.info()))
+    batch = Batch(fused, xs, ys, Ts)
+    log("batch build %.1fs, items/workgroups %s" % (time.time() - t0, batch.info()))
     ms_batch = timed(batch.launch, max(3, a.steps))
     batch.status()
     ms_fused = timed(lambda: [p.run(x, T, out=y) for p, x, y, T in zip(fused, xs, ys, Ts)], 2)

@@ -96,7 +96,16 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
         BatchGrid &g = grids[i];
         std::memset(&g, 0, sizeof g);
         const int kmax = p->r == 1 ? kBatchMaxK1 : kBatchMaxK2;
-        int k = p->exec.method == STENCIL_METHOD_GENERIC ? 1 : p->exec.k;
+        // plain and generic plans run one step per item; a fused plan runs its
+        // requested depth, else the deepest compiled one (longer items amortise
+        // the per-item fill and synchronisation; measured best on uneven batches)
+        int k = kmax;
+        if (p->opts.method == STENCIL_METHOD_GENERIC || p->opts.method == STENCIL_METHOD_PLAIN)
+            k = 1;
+        else if (p->opts.fused_k > 0)
+            k = p->opts.fused_k;
+        else if (flags & 1)
+            k = p->exec.k;
         k = std::max(1, std::min(k, kmax));
         const int64_t Ti = T[i];
         g.k = k;
@@ -109,7 +118,9 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
         g.r = p->r;
         g.box = p->kind == STENCIL_BOX ? 1 : 0;
         g.bc = p->bc;
-        const int chunk = p->exec.chunk > 0 ? p->exec.chunk : kBatchChunk;
+        // an explicitly requested chunk wins; a tuned or measured single-grid chunk
+        // does not carry over (it is chosen to fill the GPU with one grid)
+        const int chunk = p->opts.chunk > 0 ? p->opts.chunk : kBatchChunk;
         const Geometry geo = stream_geometry(2, p->r, k, VariantShape{kBatchVX, kBatchNW, 1}, p->n0, 1, p->n2, chunk);
         if (!geo.ok) return fail(STENCIL_E_INVALID, "grid %d has no valid tiling", i);
         g.tiles_x = geo.tiles_x;
@@ -122,10 +133,17 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
         for (int q = 0; q < W * W; ++q) g.coef[q] = p->dense[q];
         max_pass = std::max(max_pass, g.npass);
     }
-    // work list: pass-major
+    // work list: pass-major; within a pass, grids with the longest remaining chain
+    // of passes first (they bound the makespan)
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const int64_t wx = (int64_t)grids[x].npass * grids[x].nblk, wy = (int64_t)grids[y].npass * grids[y].nblk;
+        return grids[x].npass != grids[y].npass ? grids[x].npass > grids[y].npass : wx > wy;
+    });
     std::vector<BatchItem> items;
     for (int pass = 0; pass < max_pass; ++pass)
-        for (int i = 0; i < n; ++i)
+        for (int i : order)
             if (pass < grids[i].npass)
                 for (int b = 0; b < grids[i].nblk; ++b) items.push_back(BatchItem{i, pass, b, 0});
     // one device allocation

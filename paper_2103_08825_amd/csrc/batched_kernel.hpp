@@ -10,7 +10,10 @@ constexpr int kBatchVX = 1;
 constexpr int kBatchNW = 4;
 constexpr int kBatchMaxK1 = 8;  // fused steps compiled for order-1 stencils
 constexpr int kBatchMaxK2 = 4;  // ... for order-2 stencils
-constexpr int kBatchChunk = 128;
+// rows per work item: large enough that an item's fill (k(2r+1) extra steps) and
+// bookkeeping are small, small enough that a grid's pass splits into many items
+// (measured on the 256-grid workload: 256 beats 64, 128 and 1024)
+constexpr int kBatchChunk = 256;
 // A wait gives up after this many ticks of the 100 MHz real-time counter
 // (about one second), or at once when another workgroup already gave up.
 constexpr uint64_t kWaitTicks = 100000000ull;

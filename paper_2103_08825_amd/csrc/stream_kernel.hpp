@@ -73,6 +73,7 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);  // the wave's index, in a scalar register
     const S *__restrict__ src = static_cast<const S *>(a.src);
     S *__restrict__ dst = static_cast<S *>(a.dst);
     const bool periodic = (a.bc == 1);
@@ -209,6 +210,18 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
         static_for<0, K>([&](auto JJ) {
             constexpr int j = K - decltype(JJ)::value;  // level 1..K
             constexpr int in_slot = posmod(PH - 1 - (j - 1) * (R + 1), W);
+            // Skip work no kept point depends on (uniform branches): the incoming
+            // plane feeds level-j planes [q, q+2R], q = the plane completed now; level
+            // j is needed only on [z_out0 - (K-j)R, z_out1 - 1 + (K-j)R].  A wave whose
+            // rows all lie within j*R of the widened tile's y edge holds only
+            // recomputed halo at level j.  Measured: worth it for order-2 stencils;
+            // for order 1 the branches cost more (they split the step into blocks the
+            // scheduler cannot interleave) than the skipped work saves.
+            constexpr bool kSkip = (R >= 2);
+            const int q = zs + s - j * (R + 1);
+            const bool needed = (q <= z_out1 - 1 + (K - j) * R) && (q + 2 * R >= z_out0 - (K - j) * R);
+            const bool wave_on = (DIM == 2) || ((wvu + 1) * RW > j * R && wvu * RW < NW * RW - j * R);
+            const bool work = !kSkip || (needed && wave_on);
             C ext[EXT][VX];
 #pragma unroll
             for (int i = 0; i < RW; ++i)
@@ -241,6 +254,9 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
             if constexpr (j == 1) {
                 // slot of plane s-1 is free again: fetch plane s-1+W into it
                 load_next(pf[in_slot]);
+            }
+            if constexpr (kSkip) {
+                if (!work) return;
             }
             // x-shifted copies of every row: xs[e][v][dx+R] = row e at column v+dx
             C xs[EXT][VX][W];
