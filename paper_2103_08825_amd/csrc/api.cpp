@@ -139,16 +139,16 @@ struct Choice {
 };
 static const Choice kChoices[] = {
     // 3D FP32: 7-point, 27-point, 13-point
-    {3, 1, STENCIL_STAR, 1, 6, 5, 128, 3, 0}, {3, 1, STENCIL_BOX, 1, 4, 3, 128, 4, 32},
+    {3, 1, STENCIL_STAR, 1, 5, 5, 128, 3, 0}, {3, 1, STENCIL_BOX, 1, 4, 3, 128, 4, 32},
     {3, 2, STENCIL_STAR, 1, 4, 2, 64, 1, 0},
     // 3D 16-bit storage
-    {3, 1, STENCIL_STAR, 2, 4, 3, 64, 1, 32}, {3, 1, STENCIL_BOX, 2, 4, 2, 32, 4, 32},
+    {3, 1, STENCIL_STAR, 2, 1, 3, 64, 1, 32}, {3, 1, STENCIL_BOX, 2, 4, 2, 32, 4, 32},
     {3, 2, STENCIL_STAR, 2, 4, 2, 64, 4, 32},
     // 3D FP64
     {3, 1, STENCIL_STAR, 0, 1, 2, 32, 1, 0}, {3, 1, STENCIL_BOX, 0, 1, 2, 32, 1, 32},
     {3, 2, STENCIL_STAR, 0, 1, 2, 0, 1, 32},
     // 2D FP32: 5-point, 9-point
-    {2, 1, STENCIL_STAR, 1, 2, 7, 0, 2, 64}, {2, 1, STENCIL_BOX, 1, 2, 7, 64, 2, 64},
+    {2, 1, STENCIL_STAR, 1, 2, 8, 64, 2, 64}, {2, 1, STENCIL_BOX, 1, 2, 7, 0, 2, 64},
 };
 
 static const Choice *measured_choice(const stencil_plan *p) {

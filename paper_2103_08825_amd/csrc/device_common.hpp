@@ -165,6 +165,80 @@ template <int B, int E, typename F> __device__ __forceinline__ void static_for(F
     }
 }
 
+// t[i] += c * (x[i] held by lane l + S) for N independent rows i, 0 outside
+// the wave.  For FP32 the last one-lane step is a DPP operand of the FMA itself
+// (v_fmac_f32 with a wave_shr:1 / wave_shl:1 source), so a neighbour in the
+// adjacent lane costs one VALU instruction instead of a lane move plus an FMA;
+// a source lane outside the wave reads 0 (bound_ctrl) and leaves t unchanged.
+// The product is rounded once inside the fused multiply-add, exactly as in
+// fma_c(c, x, t).  A DPP instruction must not read a register that a VALU
+// instruction wrote in the two preceding wait states; the compiler's hazard
+// pass does not look inside inline assembly, so each block of up to four
+// instructions opens with its own s_nop (the instructions inside a block read
+// no register another one of them writes: the outputs are early-clobber).
+// FP64 uses lane moves (wave shifts are not available to 64-bit DPP operands).
+#define STN_DPP_FMAC(D, X, C, CTL) "v_fmac_f32_dpp " D ", " X ", " C " " CTL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+template <int S> __device__ __forceinline__ void dpp_fmac4(float c, const float *x, float *t) {
+    static_assert(S == -1 || S == 1, "one-lane shift");
+    if constexpr (S == -1) {
+        asm("s_nop 1\n\t" STN_DPP_FMAC("%0", "%4", "%8", "wave_shr:1") STN_DPP_FMAC("%1", "%5", "%8", "wave_shr:1")
+                STN_DPP_FMAC("%2", "%6", "%8", "wave_shr:1") STN_DPP_FMAC("%3", "%7", "%8", "wave_shr:1")
+            : "+&v"(t[0]), "+&v"(t[1]), "+&v"(t[2]), "+&v"(t[3])
+            : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(c));
+    } else {
+        asm("s_nop 1\n\t" STN_DPP_FMAC("%0", "%4", "%8", "wave_shl:1") STN_DPP_FMAC("%1", "%5", "%8", "wave_shl:1")
+                STN_DPP_FMAC("%2", "%6", "%8", "wave_shl:1") STN_DPP_FMAC("%3", "%7", "%8", "wave_shl:1")
+            : "+&v"(t[0]), "+&v"(t[1]), "+&v"(t[2]), "+&v"(t[3])
+            : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(c));
+    }
+}
+template <int S> __device__ __forceinline__ void dpp_fmac2(float c, const float *x, float *t) {
+    static_assert(S == -1 || S == 1, "one-lane shift");
+    if constexpr (S == -1) {
+        asm("s_nop 1\n\t" STN_DPP_FMAC("%0", "%2", "%4", "wave_shr:1") STN_DPP_FMAC("%1", "%3", "%4", "wave_shr:1")
+            : "+&v"(t[0]), "+&v"(t[1])
+            : "v"(x[0]), "v"(x[1]), "v"(c));
+    } else {
+        asm("s_nop 1\n\t" STN_DPP_FMAC("%0", "%2", "%4", "wave_shl:1") STN_DPP_FMAC("%1", "%3", "%4", "wave_shl:1")
+            : "+&v"(t[0]), "+&v"(t[1])
+            : "v"(x[0]), "v"(x[1]), "v"(c));
+    }
+}
+template <int S> __device__ __forceinline__ void dpp_fmac1(float c, const float *x, float *t) {
+    static_assert(S == -1 || S == 1, "one-lane shift");
+    if constexpr (S == -1) {
+        asm("s_nop 1\n\t" STN_DPP_FMAC("%0", "%1", "%2", "wave_shr:1")
+            : "+&v"(t[0])
+            : "v"(x[0]), "v"(c));
+    } else {
+        asm("s_nop 1\n\t" STN_DPP_FMAC("%0", "%1", "%2", "wave_shl:1")
+            : "+&v"(t[0])
+            : "v"(x[0]), "v"(c));
+    }
+}
+#undef STN_DPP_FMAC
+
+template <int S, int N> __device__ __forceinline__ void fma_shift_rows(float c, const float (&x)[N], float (&t)[N]) {
+    static_assert(S != 0, "no shift");
+    if constexpr (S < -1 || S > 1) {
+        float y[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) y[i] = dpp32<(S < 0) ? kDppWaveShr1 : kDppWaveShl1>(x[i]);
+        fma_shift_rows<(S < 0) ? S + 1 : S - 1, N>(c, y, t);
+    } else {
+        constexpr int S1 = S;
+        static_for<0, N / 4>([&](auto B_) { dpp_fmac4<S1>(c, x + 4 * decltype(B_)::value, t + 4 * decltype(B_)::value); });
+        constexpr int done = N / 4 * 4;
+        if constexpr (N - done >= 2) dpp_fmac2<S1>(c, x + done, t + done);
+        if constexpr ((N - done) % 2 == 1) dpp_fmac1<S1>(c, x + N - 1, t + N - 1);
+    }
+}
+template <int S, int N> __device__ __forceinline__ void fma_shift_rows(double c, const double (&x)[N], double (&t)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = fma_c(c, lane_shift<S>(x[i]), t[i]);
+}
+
+
 constexpr int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 constexpr int posmod(int a, int b) { return ((a % b) + b) % b; }
 

@@ -258,40 +258,64 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
             if constexpr (kSkip) {
                 if (!work) return;
             }
-            // x-shifted copies of every row: xs[e][v][dx+R] = row e at column v+dx
-            C xs[EXT][VX][W];
-            static_for<0, EXT>([&](auto E_) {
-                constexpr int E = decltype(E_)::value;
-                static_for<0, VX>([&](auto V_) {
-                    constexpr int V = decltype(V_)::value;
-                    static_for<-R, R + 1>([&](auto DX_) {
-                        constexpr int DX = decltype(DX_)::value;
-                        xs[E][V][DX + R] = xval<DX, V, VX>(ext[E]);
+            // FP64: lane-shifted copies of every row, shared by all their uses
+            // (xs[e][v][dx+R] = row e at column v+dx); FP32 shifts inside each FMA
+            constexpr bool kShareShifts = sizeof(C) == 8;
+            C xs[kShareShifts ? EXT : 1][VX][W];
+            if constexpr (kShareShifts) {
+                static_for<0, EXT>([&](auto E_) {
+                    constexpr int E = decltype(E_)::value;
+                    static_for<0, VX>([&](auto V_) {
+                        constexpr int V = decltype(V_)::value;
+                        static_for<-R, R + 1>([&](auto DX_) {
+                            constexpr int DX = decltype(DX_)::value;
+                            xs[E][V][DX + R] = xval<DX, V, VX>(ext[E]);
+                        });
                     });
                 });
-            });
-            // scatter plane m into output planes m-dz of level j
+            }
+            // scatter plane m into output planes m-dz of level j.  Every point's
+            // terms are added in the canonical offset order; the loop runs over
+            // offsets outside and rows inside, so the rows' lane-shifted terms of
+            // one offset issue together.
             static_for<-R, R + 1>([&](auto DZ_) {
                 constexpr int DZ = decltype(DZ_)::value;
                 constexpr int slot = posmod(PH - 1 - (j - 1) * (R + 1) - DZ, W);
+                C t[VX][RW];
 #pragma unroll
-                for (int i = 0; i < RW; ++i) {
-                    static_for<0, VX>([&](auto V_) {
-                        constexpr int V = decltype(V_)::value;
-                        C t = (DZ == -R) ? C(0) : acc[j - 1][slot][i][V];
-                        static_for<-YR, YR + 1>([&](auto DY_) {
-                            constexpr int DY = decltype(DY_)::value;
-                            static_for<-R, R + 1>([&](auto DX_) {
-                                constexpr int DX = decltype(DX_)::value;
-                                if constexpr (is_member<DIM, R, BOX, DZ, DY, DX>()) {
-                                    const C c = a.coef[dense_index<DIM, R, DZ, DY, DX>()];
-                                    t = fma_c(c, xs[YR + i + DY][V][DX + R], t);
+                for (int i = 0; i < RW; ++i)
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) t[v][i] = (DZ == -R) ? C(0) : acc[j - 1][slot][i][v];
+                static_for<-YR, YR + 1>([&](auto DY_) {
+                    constexpr int DY = decltype(DY_)::value;
+                    static_for<-R, R + 1>([&](auto DX_) {
+                        constexpr int DX = decltype(DX_)::value;
+                        if constexpr (is_member<DIM, R, BOX, DZ, DY, DX>()) {
+                            const C c = a.coef[dense_index<DIM, R, DZ, DY, DX>()];
+                            static_for<0, VX>([&](auto V_) {
+                                constexpr int V = decltype(V_)::value;
+                                constexpr int sh = floordiv(V + DX, VX);  // lanes away
+                                constexpr int m = V + DX - sh * VX;        // column in that lane
+                                if constexpr (kShareShifts) {
+#pragma unroll
+                                    for (int i = 0; i < RW; ++i) t[V][i] = fma_c(c, xs[YR + i + DY][V][DX + R], t[V][i]);
+                                } else if constexpr (sh == 0) {
+#pragma unroll
+                                    for (int i = 0; i < RW; ++i) t[V][i] = fma_c(c, ext[YR + i + DY][m], t[V][i]);
+                                } else {
+                                    C x[RW];
+#pragma unroll
+                                    for (int i = 0; i < RW; ++i) x[i] = ext[YR + i + DY][m];
+                                    fma_shift_rows<sh, RW>(c, x, t[V]);
                                 }
                             });
-                        });
-                        acc[j - 1][slot][i][V] = t;
+                        }
                     });
-                }
+                });
+#pragma unroll
+                for (int i = 0; i < RW; ++i)
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) acc[j - 1][slot][i][v] = t[v][i];
             });
             // plane m-R of level j is complete: apply the zero halo
             if constexpr (j < K && MASK) {
