@@ -83,7 +83,10 @@ typedef struct stencil_opts {
     int autotune; /* nonzero: time the candidate (variant, k, chunk) choices on the first
                      run (or on stencil_autotune) and keep the fastest */
     int chunk;    /* 2D/3D fused kernels: output planes per workgroup along axis 0;
-                     0 = choose */
+                     0 = choose (the measured default; for k >= 2 otherwise the
+                     chunk count that minimises rounds of resident workgroups x
+                     stream length, from the kernel's occupancy on the current
+                     device) */
 } stencil_opts;
 
 /* What a plan resolved to (stencil_plan_info). */

@@ -104,6 +104,18 @@ SweepLauncher pass_launcher(const stencil_plan *p, const Exec &ex, int k) {
     return find_launcher(KernelKey{p->dtype, p->dim, p->r, box_key(p), ex.variant, k});
 }
 
+// chunk 0 ("automatic") of a fused 2D/3D launch: balanced over the workgroups
+// the device holds at once.  Stays 0 (the geometry's own rule: many short
+// chunks) for one step per launch, whose workgroups wait on memory rather than
+// compute (measured: the balanced rule loses 7% there), and when the
+// residency cannot be queried.
+static int auto_chunk(const stencil_plan *p, int variant, int k) {
+    VariantShape v;
+    if (p->dim < 2 || k < 2 || !shape_of(p->dim, variant, &v)) return 0;
+    const int resident = resident_blocks(KernelKey{p->dtype, p->dim, p->r, box_key(p), variant, k});
+    return balanced_chunk(p->dim, p->r, k, v, p->n0, p->n1, p->n2, resident);
+}
+
 // default variant: widest lanes that fit the shape, else the first registered
 static int default_variant(const stencil_plan *p, int need_k) {
     int best = 0;
@@ -130,8 +142,9 @@ static int default_k(const stencil_plan *p, int variant) {
 }
 
 // Measured defaults (MI355X, 512^3 3D and 8192^2 2D grids; each the fastest
-// (variant, k, chunk) of a sweep over all compiled choices).  Shape-independent;
-// stencil_autotune refines them for a given plan.
+// (variant, k, chunk) of a sweep over all compiled choices; chunk 0 = balanced
+// over the resident workgroups for the plan's shape).  stencil_autotune
+// refines them for a given plan.
 struct Choice {
     int dim, r, kind, dclass;  // dclass: 0 FP64, 1 FP32, 2 16-bit
     int variant, k, chunk;     // fused
@@ -139,16 +152,16 @@ struct Choice {
 };
 static const Choice kChoices[] = {
     // 3D FP32: 7-point, 27-point, 13-point
-    {3, 1, STENCIL_STAR, 1, 5, 5, 128, 3, 0}, {3, 1, STENCIL_BOX, 1, 4, 3, 128, 4, 32},
-    {3, 2, STENCIL_STAR, 1, 4, 2, 64, 1, 0},
+    {3, 1, STENCIL_STAR, 1, 5, 5, 0, 3, 0}, {3, 1, STENCIL_BOX, 1, 4, 3, 128, 4, 32},
+    {3, 2, STENCIL_STAR, 1, 4, 2, 64, 4, 0},
     // 3D 16-bit storage
-    {3, 1, STENCIL_STAR, 2, 1, 3, 64, 1, 32}, {3, 1, STENCIL_BOX, 2, 4, 2, 32, 4, 32},
+    {3, 1, STENCIL_STAR, 2, 1, 3, 64, 1, 0}, {3, 1, STENCIL_BOX, 2, 4, 2, 32, 4, 32},
     {3, 2, STENCIL_STAR, 2, 4, 2, 64, 4, 32},
     // 3D FP64
-    {3, 1, STENCIL_STAR, 0, 1, 2, 32, 1, 0}, {3, 1, STENCIL_BOX, 0, 1, 2, 32, 1, 32},
+    {3, 1, STENCIL_STAR, 0, 1, 2, 0, 1, 32}, {3, 1, STENCIL_BOX, 0, 1, 2, 32, 1, 32},
     {3, 2, STENCIL_STAR, 0, 1, 2, 0, 1, 32},
     // 2D FP32: 5-point, 9-point
-    {2, 1, STENCIL_STAR, 1, 2, 8, 64, 2, 64}, {2, 1, STENCIL_BOX, 1, 2, 7, 0, 2, 64},
+    {2, 1, STENCIL_STAR, 1, 2, 8, 0, 2, 64}, {2, 1, STENCIL_BOX, 1, 2, 8, 0, 2, 64},
 };
 
 static const Choice *measured_choice(const stencil_plan *p) {
@@ -214,7 +227,7 @@ static int resolve_exec(stencil_plan *p) {
     ex.method = method;
     ex.variant = variant;
     ex.k = k;
-    ex.chunk = chunk;
+    ex.chunk = chunk > 0 ? chunk : auto_chunk(p, variant, k);
     p->exec = ex;
     return STENCIL_OK;
 }
@@ -411,7 +424,7 @@ static int autotune_impl(stencil_plan *p, hipStream_t st) {
                     if (c >= 2 * k * (2 * p->r + 1) && c < p->n0) chunks.push_back(c);
             }
             for (int c : chunks) {
-                Exec ex{p->exec.method, v, k, c};
+                Exec ex{p->exec.method, v, k, c > 0 ? c : auto_chunk(p, v, k)};
                 float ms = 0;
                 rc = time_exec(p, ex, st, &ms);
                 if (rc != STENCIL_OK) return rc;

@@ -53,6 +53,20 @@ hipError_t launch_stream(const SweepLaunch &L, hipStream_t st) {
     return hipGetLastError();
 }
 
+// workgroups of one streaming kernel a compute unit holds (queried once)
+template <typename S, int DIM, int R, bool BOX, int K, int VX, int NW, int RW> int occupancy_stream() {
+    static int per = -1;
+    if (per < 0) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &v, reinterpret_cast<const void *>(&stream_kernel<S, DIM, R, BOX, K, VX, NW, RW>), 64 * NW, 0) !=
+            hipSuccess)
+            v = 0;
+        per = v;
+    }
+    return per;
+}
+
 template <typename S, int R, int K, int VX, int NW>
 hipError_t launch_seg1d(const SweepLaunch &L, hipStream_t st) {
     using C = typename ComputeOf<S>::type;
@@ -78,7 +92,8 @@ struct StreamReg {
         constexpr int vid = variant_id<DIM>(VX, NW, RW);
         static_assert(vid > 0, "shape is not a listed variant");
         register_launcher(KernelKey{storage_dtype<S>(), DIM, R, BOX ? 1 : 0, vid, K},
-                          &launch_stream<S, DIM, R, BOX, K, VX, NW, RW>);
+                          &launch_stream<S, DIM, R, BOX, K, VX, NW, RW>,
+                          &occupancy_stream<S, DIM, R, BOX, K, VX, NW, RW>);
     }
 };
 

@@ -65,6 +65,35 @@ inline Geometry stream_geometry(int dim, int r, int k, VariantShape v, int64_t n
     return g;
 }
 
+// Chunk of the streamed axis that balances the launch over `resident`
+// co-resident workgroups: a workgroup's time grows with its stream length
+// (chunk + K(2R+1) steps of fill and drain) and the launch takes
+// ceil(blocks / resident) rounds of workgroups, so pick the number of chunks
+// that minimises rounds x stream length (fewer chunks on ties).  0 if the
+// residency is unknown.
+inline int balanced_chunk(int dim, int r, int k, VariantShape v, int64_t n0, int64_t n1, int64_t n2,
+                          int resident) {
+    if (resident <= 0 || dim < 2) return 0;
+    const Geometry g = stream_geometry(dim, r, k, v, n0, n1, n2, (int)(n0 < 0x7fffffff ? n0 : 0x7fffffff));
+    if (!g.ok) return 0;
+    const int64_t nxy = g.nblocks;  // one chunk
+    const int64_t fill = (int64_t)k * (2 * r + 1);
+    const int64_t cmin = 2 * fill > 8 ? 2 * fill : 8;
+    int64_t best_c = n0, best_cost = -1;
+    const int64_t max_chunks = n0 / cmin > 1 ? n0 / cmin : 1;
+    for (int64_t nc = 1; nc <= max_chunks && nc <= 4096; ++nc) {
+        const int64_t c = (n0 + nc - 1) / nc;
+        const int64_t chunks = (n0 + c - 1) / c;
+        const int64_t rounds = (nxy * chunks + resident - 1) / resident;
+        const int64_t cost = rounds * (c + fill);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best_c = c;
+        }
+    }
+    return (int)best_c;
+}
+
 inline Geometry seg1d_geometry(int r, int k, VariantShape v, int64_t n) {
     Geometry g{};
     g.threads = 64 * v.nw;

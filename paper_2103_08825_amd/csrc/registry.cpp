@@ -14,23 +14,41 @@ std::mutex &reg_mutex() {
     static std::mutex m;
     return m;
 }
-std::map<Key, SweepLauncher> &reg_map() {
-    static std::map<Key, SweepLauncher> m;
+struct Entry {
+    SweepLauncher fn;
+    OccupancyFn occ;
+};
+std::map<Key, Entry> &reg_map() {
+    static std::map<Key, Entry> m;
     return m;
 }
 Key tup(const KernelKey &k) { return Key(k.dtype, k.dim, k.r, k.box, k.variant, k.k); }
 
 }  // namespace
 
-void register_launcher(const KernelKey &key, SweepLauncher fn) {
+void register_launcher(const KernelKey &key, SweepLauncher fn, OccupancyFn occ) {
     std::lock_guard<std::mutex> g(reg_mutex());
-    reg_map()[tup(key)] = fn;
+    reg_map()[tup(key)] = Entry{fn, occ};
 }
 
 SweepLauncher find_launcher(const KernelKey &key) {
     std::lock_guard<std::mutex> g(reg_mutex());
     auto it = reg_map().find(tup(key));
-    return it == reg_map().end() ? nullptr : it->second;
+    return it == reg_map().end() ? nullptr : it->second.fn;
+}
+
+int resident_blocks(const KernelKey &key) {
+    OccupancyFn occ = nullptr;
+    {
+        std::lock_guard<std::mutex> g(reg_mutex());
+        auto it = reg_map().find(tup(key));
+        if (it != reg_map().end()) occ = it->second.occ;
+    }
+    if (!occ) return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus * occ();
 }
 
 int registered_max_k(int dtype, int dim, int r, int box, int variant) {

@@ -13,8 +13,13 @@ struct KernelKey {
     int dtype, dim, r, box, variant, k;
 };
 
-void register_launcher(const KernelKey &key, SweepLauncher fn);
+// workgroups of one kernel that a compute unit holds at once (0 if unknown)
+using OccupancyFn = int (*)();
+
+void register_launcher(const KernelKey &key, SweepLauncher fn, OccupancyFn occ = nullptr);
 SweepLauncher find_launcher(const KernelKey &key);
+// workgroups of the kernel behind `key` the whole device holds at once (0 if unknown)
+int resident_blocks(const KernelKey &key);
 // largest k registered for (dtype, dim, r, box, variant); 0 if none
 int registered_max_k(int dtype, int dim, int r, int box, int variant);
 // every registered key
