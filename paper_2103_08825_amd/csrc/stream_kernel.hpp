@@ -370,11 +370,24 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
     for (int i = 0; i < RW; ++i)
 #pragma unroll
         for (int v = 0; v < VX; ++v) pf[W - 1][i][v] = C(0);
+    // With kWholeBlocks the stream runs in whole blocks of W steps (up to W-1
+    // steps past its end, which load and store nothing).  A partial last block
+    // makes the ring slots conditional at the loop back-edge; the register copies
+    // that merge them wait for the loads in flight, which shortens the prefetch,
+    // but they also bound the registers the loads hold.  Measured on 512^3: whole
+    // blocks win for the 27-point box and the order-2 star (5-9%); for the FP32
+    // 7-point star they push the deeper fused kernels into spills, and they cost
+    // FP64 and 16-bit storage a few per cent.
+    constexpr bool kWholeBlocks = (BOX || R >= 2) && sizeof(C) == 4;
     auto run = [&](auto MASK_) {
         for (int s0 = 0; s0 < nsteps; s0 += W) {
             static_for<0, W>([&](auto PH_) {
                 const int s = s0 + decltype(PH_)::value;
-                if (s < nsteps) step(PH_, MASK_, s);
+                if constexpr (kWholeBlocks) {
+                    step(PH_, MASK_, s);
+                } else {
+                    if (s < nsteps) step(PH_, MASK_, s);
+                }
             });
         }
     };
