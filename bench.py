@@ -85,6 +85,26 @@ def cpu_baseline(u0_f64, coeffs, r, kind, bc, budget_s=12.0):
             "seconds": secs}
 
 
+def launch_probe(plan, buf, k, n):
+    """Mean duration of one fused launch (k steps, one pass) over n launches,
+    each bracketed by HIP events on torch's current stream; the launches
+    ping-pong between `buf` and a second field."""
+    import torch
+    other = torch.empty_like(buf)
+    bufs = [buf, other]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    plan.run(bufs[0], k, out=bufs[1])
+    torch.cuda.synchronize()
+    for i in range(n):
+        ev[i][0].record()
+        plan.run(bufs[i % 2], k, out=bufs[(i + 1) % 2])
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / n
+    del other
+    return ms
+
+
 def bench_batched(a):
     """256 independent 2D FP32 grids (sides log-uniform in [64, 2048], 5-point star
     or 9-point box, T uniform in [10, 200], zero halo): one graph-captured
@@ -208,6 +228,8 @@ def main(argv=None):
     points = float(np.prod(case.shape))
     gst = points * T / (ms * 1e-3) / 1e9
     log("fused: %.3f ms/step (sweep %.3f ms), %.1f GStencil/s" % (ms, ms_sweep, gst))
+    probe_ms = launch_probe(fused, y, k, 2 * ((T + k - 1) // k))
+    log("fused k=%d launch: %.4f ms (HIP events around each of %d launches)" % (k, probe_ms, 2 * ((T + k - 1) // k)))
 
     plain_rec = None
     if not a.no_plain:
@@ -223,9 +245,11 @@ def main(argv=None):
         plain.close()
 
     # roofline of the dominant kernel (the fused pass): algorithmic bytes per launch
-    # = one read and one write of the field; its launches share the sweep time in
-    # proportion to the steps each advances
-    launch_ms = ms_sweep * k / T
+    # = one read and one write of the field, over the launch duration measured with
+    # events around single launches right after the timed sweeps (the sweep time
+    # shared out in proportion to the steps each launch advances agrees within a
+    # few per cent: launch_ms_from_sweep)
+    launch_ms = probe_ms
     alg_bytes = 2.0 * 4 * points
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     traffic = None
@@ -238,7 +262,7 @@ def main(argv=None):
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "stream_kernel<float,3,R=1,star,K=%d> variant %d" % (k, info["variant"]),
-            "launch_ms": launch_ms}
+            "launch_ms": launch_ms, "launch_ms_from_sweep": ms_sweep * k / T}
 
     # the same kernel seen from the vector ALU: useful FMAs (7 per point-step, k steps
     # per launch) against the FP32 vector peak without packed math (256 CU x 64 lanes

@@ -162,7 +162,7 @@ int stencil_run_batched(stencil_plan *const *plans, int n, const void *const *d_
  * one step for plans created with the plain or generic method, else the deepest
  * depth the batched kernel compiles (8 for r = 1, 4 for r = 2), or the tuned
  * depth when flags bit 0 is set; a pass splits into work items of opts.chunk
- * rows (default 256).  flags: bit 0 = autotune each distinct plan first and
+ * rows (default 128).  flags: bit 0 = autotune each distinct plan first and
  * take its tuned depth. */
 int stencil_batch_create(stencil_batch **out, stencil_plan *const *plans, int n,
                          const void *const *d_in, void *const *d_out, const int64_t *T,

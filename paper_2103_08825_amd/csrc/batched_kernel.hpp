@@ -12,8 +12,9 @@ constexpr int kBatchMaxK1 = 8;  // fused steps compiled for order-1 stencils
 constexpr int kBatchMaxK2 = 4;  // ... for order-2 stencils
 // rows per work item: large enough that an item's fill (k(2r+1) extra steps) and
 // bookkeeping are small, small enough that a grid's pass splits into many items
-// (measured on the 256-grid workload: 256 beats 64, 128 and 1024)
-constexpr int kBatchChunk = 256;
+// and a long chain of passes stays short (measured on the uneven 256-grid
+// workload: 128 beats 64, 256 and 512)
+constexpr int kBatchChunk = 128;
 // A wait gives up after this many ticks of the 100 MHz real-time counter
 // (about one second), or at once when another workgroup already gave up.
 constexpr uint64_t kWaitTicks = 100000000ull;
@@ -92,12 +93,25 @@ __global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs 
     // separate lane-0 regions around the back-edge (count at the end, take at
     // the top) can otherwise be merged into a loop of their own that lane 0
     // enters only after the rest of its wave has left -- which it never does.
-    int done_grid = -1;  // grid of the item finished in the previous iteration
+    //
+    // Memory ordering.  An item of pass p > 0 reads what the items of pass p-1
+    // of its grid wrote, possibly on another XCD (whose L2 is not coherent with
+    // this one).  The producer's waves first wait until their own stores have
+    // reached L2 (s_waitcnt 0) and meet at a barrier; lane 0 then issues one
+    // agent-scope release (which writes back this XCD's L2) before counting the
+    // item.  The consumer's lane 0 polls the count with relaxed loads and issues
+    // one agent-scope acquire (which invalidates this compute unit's caches)
+    // before the barrier that releases the other waves.  Items of a grid's last
+    // pass are read by nobody (the kernel's end publishes them) and items of
+    // pass 0 read only the inputs, so they skip the release and the acquire.
+    int done_grid = -1;  // grid whose item (not of its last pass) finished in the previous iteration
     for (;;) {
-        __syncthreads();  // the previous item is fully processed and fenced
+        __syncthreads();  // every wave's stores of the previous item are in L2
         if (threadIdx.x == 0) {
-            if (done_grid >= 0)
-                __hip_atomic_fetch_add(a.counters + done_grid, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (done_grid >= 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_fetch_add(a.counters + done_grid, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             item_sh = atomicAdd(a.cursor, 1);
         }
         __syncthreads();
@@ -122,15 +136,16 @@ __global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs 
                     }
                     __builtin_amdgcn_s_sleep(8);
                 }
+                // the previous pass's stores (other XCDs' included) become visible
+                // to every wave of this workgroup once they pass the barrier below
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             ok_sh = ok;
         }
         __syncthreads();
-        // every wave sees the previous pass's stores (other XCDs' L2s included)
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int ok = __builtin_amdgcn_readfirstlane(ok_sh);
+        const int npass = __builtin_amdgcn_readfirstlane(g.npass);
         if (ok) {
-            const int npass = __builtin_amdgcn_readfirstlane(g.npass);
             const int krem = __builtin_amdgcn_readfirstlane(g.krem);
             const int k = ipass < npass - 1 || krem == 0 ? __builtin_amdgcn_readfirstlane(g.k) : krem;
             const int r = __builtin_amdgcn_readfirstlane(g.r);
@@ -147,9 +162,13 @@ __global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs 
                     dispatch_k<S, 2, false, kBatchMaxK2>(g, ipass, iblk, k);
             }
         }
-        // publish this block's stores; lane 0 counts the item after the next barrier
-        __threadfence();
-        done_grid = grid;
+        if (ipass < npass - 1) {
+            // this wave's stores have reached L2 before lane 0's release
+            __builtin_amdgcn_s_waitcnt(0);
+            done_grid = grid;
+        } else {
+            done_grid = -1;
+        }
     }
 }
 
