@@ -157,6 +157,58 @@ def bench_batched(a):
     return 0
 
 
+def bench_table1(a):
+    """The six problems of the paper's evaluation table in FP64 (zero halo, T=1000):
+    the library's default fused sweep and the plain one-step sweep of each, as one
+    JSON line; `value` is total point-steps over total fused time."""
+    import torch
+    from paper_2103_08825_amd import Plan, workloads as W
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    rows, tot_work, tot_ms = {}, 0.0, 0.0
+    for name, shape, r, kind in W.TABLE1:
+        case = W.case_table1(name)
+        x = torch.from_numpy(case.u0).cuda()
+        y = torch.empty_like(x)
+        work = float(np.prod(shape)) * case.T
+        fused = Plan(shape, r, kind, case.coeffs, case.bc, "f64")
+        ms_f = timed(lambda: fused.run(x, case.T, out=y), max(1, a.steps // 2))
+        plain = Plan(shape, r, kind, case.coeffs, case.bc, "f64", method="plain")
+        ms_p = timed(lambda: plain.run(x, case.T, out=y), 1)
+        info = fused.info()
+        rows[name] = {"shape": list(shape), "npts": case.npts, "T": case.T,
+                      "fused": {"GStencil/s": work / ms_f / 1e6, "ms": ms_f, "k": info["fused_k"],
+                                "method": info["method"], "variant": info["variant"],
+                                "tile": list(info["tile"])},
+                      "plain": {"GStencil/s": work / ms_p / 1e6, "ms": ms_p}}
+        log("%-9s %-16s fused k=%d %8.1f GStencil/s (%.2f ms)   plain %7.1f GStencil/s (%.2f ms)"
+            % (name, "x".join(map(str, shape)), info["fused_k"], work / ms_f / 1e6, ms_f, work / ms_p / 1e6, ms_p))
+        tot_work += work
+        tot_ms += ms_f
+        fused.close()
+        plain.close()
+        del x, y
+    rec = {"metric": "GStencil/s, the paper's Table 1 problems (FP64, T=1000, zero halo)",
+           "unit": "GStencil/s", "value": tot_work / tot_ms / 1e6, "ms_per_step": tot_ms, "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": "1D3P/1D5P 10240000, 2D5P/2D9P 3000^2, 3D7P/3D27P 128^3; T=1000 each"},
+           "problems": rows}
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,9 +224,10 @@ def main(argv=None):
     ap.add_argument("--fused-k", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--workload", choices=["3d7p", "batched"], default="3d7p",
+    ap.add_argument("--workload", choices=["3d7p", "batched", "table1"], default="3d7p",
                     help="3d7p (default): the headline sweep; batched: 256 uneven 2D grids "
-                         "in one graph-captured persistent launch vs separate sweeps")
+                         "in one graph-captured persistent launch vs separate sweeps; table1: "
+                         "the paper's six evaluation problems in FP64")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy the FP32 field (2 x 512 MiB moved per copy) --steps times; "
                          "used to scale the HBM byte counters")
@@ -210,6 +263,8 @@ def main(argv=None):
         return 0
     if a.workload == "batched":
         return bench_batched(a)
+    if a.workload == "table1":
+        return bench_table1(a)
     case = W.case_3d("3d7p", seed=0, n=n, T=T)
     log("inputs: %s %s T=%d" % (case.name, case.shape, T))
     x = torch.from_numpy(case.u0).to(torch.float32).cuda()

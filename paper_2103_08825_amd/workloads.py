@@ -113,6 +113,21 @@ def case_adjoint(seed: int = 0, n: int = 256, T: int = 100) -> Case:
     return make_case("adj3d7p", (n, n, n), 1, STAR, BC_PERIODIC, T, seed, target=True)
 
 
+# The six problems of the paper's evaluation (Section 4.1, Table 1): FP64, T = 1000.
+# The paper does not state a boundary rule; the zero halo is used.
+TABLE1 = (("t1_1d3p", (10_240_000,), 1, STAR), ("t1_1d5p", (10_240_000,), 2, STAR),
+          ("t1_2d5p", (3000, 3000), 1, STAR), ("t1_2d9p", (3000, 3000), 1, BOX),
+          ("t1_3d7p", (128, 128, 128), 1, STAR), ("t1_3d27p", (128, 128, 128), 1, BOX))
+
+
+def case_table1(name: str, seed: int = 0, T: int = 1000) -> Case:
+    """One of the Table 1 problems by name (t1_1d3p ... t1_3d27p), zero halo."""
+    for n, shape, r, kind in TABLE1:
+        if n == name:
+            return make_case(n, shape, r, kind, BC_ZERO, T, seed)
+    raise KeyError(name)
+
+
 @dataclasses.dataclass
 class BatchedGrid:
     shape: Tuple[int, int]
