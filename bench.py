@@ -209,6 +209,90 @@ def bench_table1(a):
     return 0
 
 
+def bench_configs(a):
+    """Every workload of the hot path, fused and plain, as one JSON line: the 1D
+    3-point FP64 sweep (262,144 points, T=200), the 2D 5-point and 9-point FP32
+    periodic sweeps (8192^2, T=100), the 3D 7-, 13- and 27-point sweeps (512^3,
+    T=64) in FP32, BF16 and FP16, and the adjoint of the 3D 7-point periodic
+    sweep (256^3 FP32, T=100, checkpoints every 10).  Rates are useful
+    point-steps per second; hbm_frac is the algorithmic traffic (one read and
+    one write of the field per launch) over 8 TB/s."""
+    import torch
+    from paper_2103_08825_amd import Plan, workloads as W
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    def sweep(case, dt, method, reps):
+        x = torch.from_numpy(case.u0).to(tdt[dt]).cuda()
+        y = torch.empty_like(x)
+        plan = Plan(case.shape, case.r, case.kind, case.coeffs, case.bc, dt, method=method)
+        ms = timed(lambda: plan.run(x, case.T, out=y), reps)
+        info = plan.info()
+        k = info["fused_k"]
+        launches = -(-case.T // k)
+        pts = float(np.prod(case.shape))
+        rec = {"GStencil/s": pts * case.T / ms / 1e6, "ms": ms, "k": k, "variant": info["variant"],
+               "tile": list(info["tile"]),
+               "hbm_frac": 2.0 * x.element_size() * pts * launches / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        plan.close()
+        return rec
+
+    out = {}
+
+    def entry(name, case, dt, reps=2):
+        f = sweep(case, dt, "auto", reps)
+        p = sweep(case, dt, "plain", 1)
+        out[name] = {"fused": f, "plain": p, "speedup": p["ms"] / f["ms"]}
+        log("%-22s fused %8.1f GStencil/s (k=%d, %.2f ms, hbm %.2f)   plain %7.1f (%.2f ms, hbm %.2f)"
+            % (name, f["GStencil/s"], f["k"], f["ms"], f["hbm_frac"], p["GStencil/s"], p["ms"], p["hbm_frac"]))
+
+    entry("1d3p_262144_f64", W.case_1d3p(), "f64")
+    for kind, nm in ((W.STAR, "2d5p"), (W.BOX, "2d9p")):
+        entry(nm + "_8192_f32_periodic", W.case_2d(kind), "f32")
+    for nm in ("3d7p", "3d13p", "3d27p"):
+        case = W.case_3d(nm)
+        for dt in ("f32", "bf16", "f16"):
+            entry("%s_512_%s" % (nm, dt), case, dt)
+        del case
+    # adjoint: forward sweep, then dL/du0 and dL/dc with checkpoints every 10 steps
+    case = W.case_adjoint()
+    x = torch.from_numpy(case.u0).float().cuda()
+    tgt = torch.from_numpy(case.target).float().cuda()
+    plan = Plan(case.shape, 1, W.STAR, case.coeffs, W.BC_PERIODIC, "f32")
+    uT = plan.run(x, case.T)
+    g = (uT - tgt).contiguous()
+    ms_f = timed(lambda: plan.run(x, case.T, out=uT), 2)
+    ms_a = timed(lambda: plan.adjoint(x, g, case.T, 10), 2)
+    pts = float(np.prod(case.shape))
+    out["adjoint_3d7p_256_f32_periodic"] = {
+        "forward_ms": ms_f, "adjoint_ms": ms_a, "T": case.T, "checkpoint_every": 10,
+        "adjoint GStencil/s": pts * case.T / ms_a / 1e6,
+        "forward+adjoint GStencil/s": pts * case.T / (ms_f + ms_a) / 1e6}
+    log("adjoint 256^3 T=100: forward %.2f ms, adjoint %.2f ms (%.1f point-steps/ns)"
+        % (ms_f, ms_a, pts * case.T / ms_a / 1e6 / 1e3))
+    plan.close()
+    rec = {"metric": "GStencil/s per workload (fused and plain)", "unit": "GStencil/s",
+           "value": out["3d7p_512_f32"]["fused"]["GStencil/s"], "n_gpus": 1, "higher_is_better": True,
+           "dtype": "mixed", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": "1D3P 262144 FP64 T=200; 2D 5P/9P 8192^2 FP32 periodic T=100; "
+                                  "3D 7P/13P/27P 512^3 FP32/BF16/FP16 T=64; adjoint 3D7P 256^3 FP32 T=100"},
+           "workloads": out}
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,10 +308,11 @@ def main(argv=None):
     ap.add_argument("--fused-k", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--workload", choices=["3d7p", "batched", "table1"], default="3d7p",
+    ap.add_argument("--workload", choices=["3d7p", "batched", "table1", "configs"], default="3d7p",
                     help="3d7p (default): the headline sweep; batched: 256 uneven 2D grids "
                          "in one graph-captured persistent launch vs separate sweeps; table1: "
-                         "the paper's six evaluation problems in FP64")
+                         "the paper's six evaluation problems in FP64; configs: every "
+                         "workload, fused and plain, and the adjoint")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy the FP32 field (2 x 512 MiB moved per copy) --steps times; "
                          "used to scale the HBM byte counters")
@@ -265,6 +350,8 @@ def main(argv=None):
         return bench_batched(a)
     if a.workload == "table1":
         return bench_table1(a)
+    if a.workload == "configs":
+        return bench_configs(a)
     case = W.case_3d("3d7p", seed=0, n=n, T=T)
     log("inputs: %s %s T=%d" % (case.name, case.shape, T))
     x = torch.from_numpy(case.u0).to(torch.float32).cuda()
