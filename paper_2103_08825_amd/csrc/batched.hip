@@ -42,23 +42,23 @@ __global__ void batch_reset(int *p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-static hipError_t launch_batched(int dtype, const BatchArgs &a, int wgs, hipStream_t st) {
+static hipError_t launch_batched(int dtype, int rmax, const BatchArgs &a, int wgs, hipStream_t st) {
     switch (dtype) {
-    case STENCIL_F64: return launch_batched_f64(a, wgs, st);
-    case STENCIL_F32: return launch_batched_f32(a, wgs, st);
-    case STENCIL_BF16: return launch_batched_bf16(a, wgs, st);
-    default: return launch_batched_f16(a, wgs, st);
+    case STENCIL_F64: return launch_batched_f64(a, rmax, wgs, st);
+    case STENCIL_F32: return launch_batched_f32(a, rmax, wgs, st);
+    case STENCIL_BF16: return launch_batched_bf16(a, rmax, wgs, st);
+    default: return launch_batched_f16(a, rmax, wgs, st);
     }
 }
 
-static int resident_workgroups(int dtype, int *out) {
+static int resident_workgroups(int dtype, int rmax, int *out) {
     int dev = 0, cus = 0, per = 0;
     STN_HIP(hipGetDevice(&dev));
     STN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const void *fn = dtype == STENCIL_F64    ? batched_kernel_f64()
-                     : dtype == STENCIL_F32  ? batched_kernel_f32()
-                     : dtype == STENCIL_BF16 ? batched_kernel_bf16()
-                                             : batched_kernel_f16();
+    const void *fn = dtype == STENCIL_F64    ? batched_kernel_f64(rmax)
+                     : dtype == STENCIL_F32  ? batched_kernel_f32(rmax)
+                     : dtype == STENCIL_BF16 ? batched_kernel_bf16(rmax)
+                                             : batched_kernel_f16(rmax);
     STN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 64 * kBatchNW, 0));
     *out = std::max(1, cus * std::max(1, per));
     return STENCIL_OK;
@@ -185,8 +185,10 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
     if (e == hipSuccess && !items.empty())
         e = hipMemcpy(base + grids_b, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(fail(STENCIL_E_DEVICE, "batch upload: %s", hipGetErrorString(e)));
+    int rmax = 1;
+    for (int i = 0; i < n; ++i) rmax = std::max(rmax, grids[i].r);
     int wgs = 0;
-    int rc = resident_workgroups(dtype, &wgs);
+    int rc = resident_workgroups(dtype, rmax, &wgs);
     if (rc != STENCIL_OK) return cleanup(rc);
     if ((int64_t)wgs > (int64_t)items.size()) wgs = (int)std::max<size_t>(1, items.size());
     int *ctr = reinterpret_cast<int *>(base + grids_b + items_b);
@@ -208,7 +210,7 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
         for (int i = 0; i < n && e1 == hipSuccess; ++i)
             if (grids[i].npass == 0)
                 e1 = hipMemcpyAsync(d_out[i], d_in[i], (size_t)plans[i]->points * eb, hipMemcpyDeviceToDevice, cap);
-        const hipError_t e2 = launch_batched(dtype, b->args, wgs, cap);
+        const hipError_t e2 = launch_batched(dtype, rmax, b->args, wgs, cap);
         e = hipStreamEndCapture(cap, &b->graph);
         if (e == hipSuccess && e1 != hipSuccess) e = e1;
         if (e == hipSuccess && e2 != hipSuccess) e = e2;

@@ -3,11 +3,17 @@
 
 namespace stn {
 
-hipError_t launch_batched_f16(const BatchArgs &a, int wgs, hipStream_t st) {
-    hipLaunchKernelGGL(batched_kernel<_Float16>, dim3(wgs), dim3(64 * kBatchNW), 0, st, a);
+hipError_t launch_batched_f16(const BatchArgs &a, int rmax, int wgs, hipStream_t st) {
+    if (rmax <= 1)
+        hipLaunchKernelGGL((batched_kernel<_Float16, 1>), dim3(wgs), dim3(64 * kBatchNW), 0, st, a);
+    else
+        hipLaunchKernelGGL((batched_kernel<_Float16, 2>), dim3(wgs), dim3(64 * kBatchNW), 0, st, a);
     return hipGetLastError();
 }
 
-const void *batched_kernel_f16() { return reinterpret_cast<const void *>(&batched_kernel<_Float16>); }
+const void *batched_kernel_f16(int rmax) {
+    return rmax <= 1 ? reinterpret_cast<const void *>(&batched_kernel<_Float16, 1>)
+                     : reinterpret_cast<const void *>(&batched_kernel<_Float16, 2>);
+}
 
 }  // namespace stn

@@ -82,7 +82,9 @@ __device__ __forceinline__ void dispatch_k(const BatchGrid &g, int pass, int blk
     });
 }
 
-template <typename S>
+// RMAX: the largest stencil order the batch holds (1 or 2); a kernel compiled for
+// order 1 only carries fewer registers, hence more waves to hide memory latency.
+template <typename S, int RMAX>
 __global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs a) {
     __shared__ int item_sh;
     __shared__ int ok_sh;
@@ -155,7 +157,7 @@ __global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs 
                     dispatch_k<S, 1, true, kBatchMaxK1>(g, ipass, iblk, k);
                 else
                     dispatch_k<S, 1, false, kBatchMaxK1>(g, ipass, iblk, k);
-            } else {
+            } else if constexpr (RMAX >= 2) {
                 if (box)
                     dispatch_k<S, 2, true, kBatchMaxK2>(g, ipass, iblk, k);
                 else
@@ -173,13 +175,13 @@ __global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs 
 }
 
 // launchers and occupancy queries, one per storage type (batched_<dtype>.hip)
-hipError_t launch_batched_f64(const BatchArgs &a, int wgs, hipStream_t st);
-hipError_t launch_batched_f32(const BatchArgs &a, int wgs, hipStream_t st);
-hipError_t launch_batched_bf16(const BatchArgs &a, int wgs, hipStream_t st);
-hipError_t launch_batched_f16(const BatchArgs &a, int wgs, hipStream_t st);
-const void *batched_kernel_f64();
-const void *batched_kernel_f32();
-const void *batched_kernel_bf16();
-const void *batched_kernel_f16();
+hipError_t launch_batched_f64(const BatchArgs &a, int rmax, int wgs, hipStream_t st);
+hipError_t launch_batched_f32(const BatchArgs &a, int rmax, int wgs, hipStream_t st);
+hipError_t launch_batched_bf16(const BatchArgs &a, int rmax, int wgs, hipStream_t st);
+hipError_t launch_batched_f16(const BatchArgs &a, int rmax, int wgs, hipStream_t st);
+const void *batched_kernel_f64(int rmax);
+const void *batched_kernel_f32(int rmax);
+const void *batched_kernel_bf16(int rmax);
+const void *batched_kernel_f16(int rmax);
 
 }  // namespace stn
