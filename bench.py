@@ -85,6 +85,22 @@ def cpu_baseline(u0_f64, coeffs, r, kind, bc, budget_s=12.0):
             "seconds": secs}
 
 
+def copy_bandwidth(x, y, reps=10):
+    """Read + write bandwidth of a device-to-device copy of the field (GB/s): the
+    practical ceiling of an HBM-bound kernel on this part."""
+    import torch
+    for _ in range(2):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * x.numel() * x.element_size() * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
 def launch_probe(plan, buf, k, n):
     """Mean duration of one fused launch (k steps, one pass) over n launches,
     each bracketed by HIP events on torch's current stream; the launches
@@ -209,6 +225,53 @@ def bench_table1(a):
     return 0
 
 
+def adjoint_rates(reps):
+    """The adjoint of the 3D 7-point periodic FP32 sweep (256^3, T=100, checkpoints
+    every 10 steps): time of the forward sweep and of stencil_adjoint."""
+    import torch
+    from paper_2103_08825_amd import Plan, workloads as W
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    case = W.case_adjoint()
+    x = torch.from_numpy(case.u0).float().cuda()
+    tgt = torch.from_numpy(case.target).float().cuda()
+    plan = Plan(case.shape, 1, W.STAR, case.coeffs, W.BC_PERIODIC, "f32")
+    uT = plan.run(x, case.T)
+    g = (uT - tgt).contiguous()
+    ms_f = timed(lambda: plan.run(x, case.T, out=uT))
+    ms_a = timed(lambda: plan.adjoint(x, g, case.T, 10))
+    pts = float(np.prod(case.shape))
+    plan.close()
+    log("adjoint 256^3 T=100: forward %.2f ms, adjoint %.2f ms" % (ms_f, ms_a))
+    return {"forward_ms": ms_f, "adjoint_ms": ms_a, "T": case.T, "checkpoint_every": 10,
+            "adjoint GStencil/s": pts * case.T / ms_a / 1e6,
+            "forward+adjoint GStencil/s": pts * case.T / (ms_f + ms_a) / 1e6}
+
+
+def bench_adjoint(a):
+    """One JSON line for the adjoint workload alone."""
+    r = adjoint_rates(max(2, a.steps // 2))
+    rec = {"metric": "point-steps/s of the adjoint sweep (dL/du0 and dL/dc)", "unit": "GStencil/s",
+           "value": r["adjoint GStencil/s"], "ms_per_step": r["adjoint_ms"], "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": "3D 7-point star 256^3 FP32, periodic, T=100, checkpoints every 10"},
+           "adjoint": r}
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def bench_configs(a):
     """Every workload of the hot path, fused and plain, as one JSON line: the 1D
     3-point FP64 sweep (262,144 points, T=200), the 2D 5-point and 9-point FP32
@@ -266,23 +329,7 @@ def bench_configs(a):
         for dt in ("f32", "bf16", "f16"):
             entry("%s_512_%s" % (nm, dt), case, dt)
         del case
-    # adjoint: forward sweep, then dL/du0 and dL/dc with checkpoints every 10 steps
-    case = W.case_adjoint()
-    x = torch.from_numpy(case.u0).float().cuda()
-    tgt = torch.from_numpy(case.target).float().cuda()
-    plan = Plan(case.shape, 1, W.STAR, case.coeffs, W.BC_PERIODIC, "f32")
-    uT = plan.run(x, case.T)
-    g = (uT - tgt).contiguous()
-    ms_f = timed(lambda: plan.run(x, case.T, out=uT), 2)
-    ms_a = timed(lambda: plan.adjoint(x, g, case.T, 10), 2)
-    pts = float(np.prod(case.shape))
-    out["adjoint_3d7p_256_f32_periodic"] = {
-        "forward_ms": ms_f, "adjoint_ms": ms_a, "T": case.T, "checkpoint_every": 10,
-        "adjoint GStencil/s": pts * case.T / ms_a / 1e6,
-        "forward+adjoint GStencil/s": pts * case.T / (ms_f + ms_a) / 1e6}
-    log("adjoint 256^3 T=100: forward %.2f ms, adjoint %.2f ms (%.1f point-steps/ns)"
-        % (ms_f, ms_a, pts * case.T / ms_a / 1e6 / 1e3))
-    plan.close()
+    out["adjoint_3d7p_256_f32_periodic"] = adjoint_rates(max(2, a.steps // 2))
     rec = {"metric": "GStencil/s per workload (fused and plain)", "unit": "GStencil/s",
            "value": out["3d7p_512_f32"]["fused"]["GStencil/s"], "n_gpus": 1, "higher_is_better": True,
            "dtype": "mixed", "data": "synthetic", "vs_baseline": None,
@@ -308,11 +355,11 @@ def main(argv=None):
     ap.add_argument("--fused-k", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--workload", choices=["3d7p", "batched", "table1", "configs"], default="3d7p",
+    ap.add_argument("--workload", choices=["3d7p", "batched", "table1", "configs", "adjoint"], default="3d7p",
                     help="3d7p (default): the headline sweep; batched: 256 uneven 2D grids "
                          "in one graph-captured persistent launch vs separate sweeps; table1: "
                          "the paper's six evaluation problems in FP64; configs: every "
-                         "workload, fused and plain, and the adjoint")
+                         "workload, fused and plain, and the adjoint; adjoint: the adjoint alone")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy the FP32 field (2 x 512 MiB moved per copy) --steps times; "
                          "used to scale the HBM byte counters")
@@ -352,6 +399,8 @@ def main(argv=None):
         return bench_table1(a)
     if a.workload == "configs":
         return bench_configs(a)
+    if a.workload == "adjoint":
+        return bench_adjoint(a)
     case = W.case_3d("3d7p", seed=0, n=n, T=T)
     log("inputs: %s %s T=%d" % (case.name, case.shape, T))
     x = torch.from_numpy(case.u0).to(torch.float32).cuda()
@@ -372,6 +421,8 @@ def main(argv=None):
     log("fused: %.3f ms/step (sweep %.3f ms), %.1f GStencil/s" % (ms, ms_sweep, gst))
     probe_ms = launch_probe(fused, y, k, 2 * ((T + k - 1) // k))
     log("fused k=%d launch: %.4f ms (HIP events around each of %d launches)" % (k, probe_ms, 2 * ((T + k - 1) // k)))
+    copy_gbs = copy_bandwidth(x, y)
+    log("device copy of the field: %.0f GB/s" % copy_gbs)
 
     plain_rec = None
     if not a.no_plain:
@@ -404,7 +455,8 @@ def main(argv=None):
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "stream_kernel<float,3,R=1,star,K=%d> variant %d" % (k, info["variant"]),
-            "launch_ms": launch_ms, "launch_ms_from_sweep": ms_sweep * k / T}
+            "launch_ms": launch_ms, "launch_ms_from_sweep": ms_sweep * k / T,
+            "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs}
 
     # the same kernel seen from the vector ALU: useful FMAs (7 per point-step, k steps
     # per launch) against the FP32 vector peak without packed math (256 CU x 64 lanes
