@@ -21,7 +21,7 @@
  *   with g(u, y) = u[y] inside the grid, 0 outside (zero halo), or
  *   u[y mod N] per axis (periodic).
  *
- * Readings taken where the paper is silent (each listed in the design doc):
+ * Readings taken where the paper is silent:
  *   - offset sets: star = {0} U {+-j e_i : 1<=j<=r}, box = {o : max|o_i| <= r};
  *   - canonical coefficient order: offsets sorted lexicographically with
  *     axis 0 (the slowest, row-major) most significant, each component
