@@ -2,15 +2,17 @@
 //
 // Each grid g runs P_g fused passes (k_g steps each, the last one T_g mod k_g
 // steps).  A pass splits into nblk_g blocks (groups of output tiles times
-// chunks of rows, exactly as a single-grid launch would).  The work list
-// holds every (pass, grid, block) item ordered by pass, then grid, then block.
-// Workgroups of one persistent kernel take items from an atomic cursor in that
-// order; an item of pass p waits until grid g's completion counter reaches
-// p * nblk_g, i.e. until every block of the previous pass has been written.
-// An item only ever waits on items earlier in the list, which workgroups that
-// are already running took first, so the list always drains.  Every wait is
-// bounded: a workgroup that spins past the limit records an error and gives up
-// the item, so the kernel ends in every case.
+// chunks of rows, exactly as a single-grid launch would).  Grids are assigned
+// whole to one of kBatchParts partitions (largest work first, to the least
+// loaded); each partition's work list holds its (pass, grid, block) items
+// ordered by pass, then grid, then block.  The workgroups serving a partition
+// take its items from the partition's atomic cursor in that order; an item of
+// pass p waits until grid g's completion counter reaches p * nblk_g, i.e. until
+// every block of the previous pass has been written.  An item only ever waits
+// on items earlier in its partition's list, which running workgroups of that
+// partition took first, so every list drains.  Every wait is bounded: a
+// workgroup that spins past the limit records an error and gives up the item,
+// so the kernel ends in every case.
 //
 // The counter reset and the persistent kernel are captured once into a HIP
 // graph; stencil_batch_launch replays it.
@@ -30,7 +32,7 @@ struct stencil_batch {
     int64_t nitems;
     int ngrids;
     int workgroups;
-    void *mem;  // one device allocation: grids, items, counters | cursor | error, scratch fields
+    void *mem;  // one device allocation: grids, items, counters | cursors | error | bounds, scratch fields
     stn::BatchArgs args;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -133,25 +135,46 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
         for (int q = 0; q < W * W; ++q) g.coef[q] = p->dense[q];
         max_pass = std::max(max_pass, g.npass);
     }
-    // work list: pass-major; within a pass, grids with the longest remaining chain
-    // of passes first (they bound the makespan)
+    // partitions: whole grids, largest work first into the least loaded partition
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
+    auto work = [&](int i) { return (double)plans[i]->points * (double)T[i]; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    std::vector<int> part_of(n, 0);
+    double load[kBatchParts] = {};
+    for (int i : order) {
+        int best = 0;
+        for (int q = 1; q < kBatchParts; ++q)
+            if (load[q] < load[best]) best = q;
+        part_of[i] = best;
+        load[best] += work(i);
+    }
+    // each partition's list: pass-major; within a pass, grids with the longest
+    // remaining chain of passes first (they bound the makespan)
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         const int64_t wx = (int64_t)grids[x].npass * grids[x].nblk, wy = (int64_t)grids[y].npass * grids[y].nblk;
         return grids[x].npass != grids[y].npass ? grids[x].npass > grids[y].npass : wx > wy;
     });
     std::vector<BatchItem> items;
-    for (int pass = 0; pass < max_pass; ++pass)
-        for (int i : order)
-            if (pass < grids[i].npass)
-                for (int b = 0; b < grids[i].nblk; ++b) items.push_back(BatchItem{i, pass, b, 0});
+    std::vector<int> part_begin(kBatchParts + 1, 0);
+    for (int q = 0; q < kBatchParts; ++q) {
+        part_begin[q] = (int)items.size();
+        for (int pass = 0; pass < max_pass; ++pass)
+            for (int i : order)
+                if (part_of[i] == q && pass < grids[i].npass)
+                    for (int b = 0; b < grids[i].nblk; ++b) items.push_back(BatchItem{i, pass, b, 0});
+    }
+    part_begin[kBatchParts] = (int)items.size();
+    if (items.size() >= (size_t)0x7fffffff) return fail(STENCIL_E_UNSUPPORTED, "batch has too many work items");
     // one device allocation
     const size_t eb = elem_bytes(dtype);
     auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t grids_b = align(sizeof(BatchGrid) * n);
     const size_t items_b = align(sizeof(BatchItem) * std::max<size_t>(1, items.size()));
-    const size_t ctr_b = align(sizeof(int) * (n + 2));
+    // counters: per grid, then the partition cursors (one line each), the error
+    // flag and the partition bounds
+    const size_t ctr_ints = (size_t)n + kBatchParts * kCursorStride + 1;
+    const size_t ctr_b = align(sizeof(int) * (ctr_ints + kBatchParts + 1));
     size_t scratch_b = 0;
     for (int i = 0; i < n; ++i)
         if (grids[i].npass > 1) scratch_b += align((size_t)plans[i]->points * eb);
@@ -184,27 +207,31 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
     e = hipMemcpy(base, grids.data(), sizeof(BatchGrid) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess && !items.empty())
         e = hipMemcpy(base + grids_b, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+    int *ctr = reinterpret_cast<int *>(base + grids_b + items_b);
+    if (e == hipSuccess)
+        e = hipMemcpy(ctr + ctr_ints, part_begin.data(), sizeof(int) * part_begin.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(fail(STENCIL_E_DEVICE, "batch upload: %s", hipGetErrorString(e)));
     int rmax = 1;
     for (int i = 0; i < n; ++i) rmax = std::max(rmax, grids[i].r);
     int wgs = 0;
     int rc = resident_workgroups(dtype, rmax, &wgs);
     if (rc != STENCIL_OK) return cleanup(rc);
-    if ((int64_t)wgs > (int64_t)items.size()) wgs = (int)std::max<size_t>(1, items.size());
-    int *ctr = reinterpret_cast<int *>(base + grids_b + items_b);
+    // whole rounds of partitions (every partition needs a resident workgroup)
+    if (wgs < kBatchParts) return cleanup(fail(STENCIL_E_UNSUPPORTED, "device holds too few workgroups"));
+    wgs = wgs / kBatchParts * kBatchParts;
     b->dtype = dtype;
     b->ngrids = n;
     b->nitems = (int64_t)items.size();
     b->workgroups = wgs;
     b->args = BatchArgs{reinterpret_cast<const BatchGrid *>(base), reinterpret_cast<const BatchItem *>(base + grids_b),
-                        b->nitems, ctr, ctr + n, ctr + n + 1};
+                        ctr + ctr_ints, ctr, ctr + n, ctr + n + kBatchParts * kCursorStride};
     STN_HIP(hipGetDevice(&b->device));
     // capture: reset counters, cursor and error flag with a kernel, then the persistent kernel
     hipStream_t cap = nullptr;
     e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(batch_reset, dim3(1), dim3(256), 0, cap, ctr, n + 2);
+        hipLaunchKernelGGL(batch_reset, dim3(1), dim3(256), 0, cap, ctr, (int)ctr_ints);
         hipError_t e1 = hipGetLastError();
         // grids with T = 0 are copies
         for (int i = 0; i < n && e1 == hipSuccess; ++i)

@@ -33,12 +33,19 @@ struct BatchItem {
     int grid, pass, blk, pad;
 };
 
+// The work list is split into kBatchParts partitions, each holding whole grids;
+// workgroup b serves partition b mod kBatchParts.  Workgroups are dispatched to
+// the XCDs round-robin, so a partition's items (and its grids' halo re-reads)
+// stay in one XCD's L2, and the partitions' cursors do not contend.
+constexpr int kBatchParts = 8;
+constexpr int kCursorStride = 32;  // ints between cursors: one 128-byte line each
+
 struct BatchArgs {
     const BatchGrid *grids;
     const BatchItem *items;
-    int64_t nitems;
-    int *counters;  // one per grid
-    int *cursor;
+    const int *part_begin;  // kBatchParts + 1 item indices
+    int *counters;          // one per grid
+    int *cursors;           // kBatchParts, kCursorStride apart
     int *error;
 };
 
@@ -88,6 +95,10 @@ template <typename S, int RMAX>
 __global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs a) {
     __shared__ int item_sh;
     __shared__ int ok_sh;
+    // Within a partition, an item only waits on earlier items of the same grid,
+    // which workgroups of the same partition (all resident) took first, so
+    // every partition's list drains.
+    //
     // Lane 0 of the workgroup does all bookkeeping in one place, between the
     // two barriers that open an iteration: it counts the item finished in the
     // previous iteration, then takes the next one.  Loop control is read back
@@ -107,6 +118,8 @@ __global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs 
     // pass are read by nobody (the kernel's end publishes them) and items of
     // pass 0 read only the inputs, so they skip the release and the acquire.
     int done_grid = -1;  // grid whose item (not of its last pass) finished in the previous iteration
+    const int part = blockIdx.x % kBatchParts;
+    const int first = a.part_begin[part], last = a.part_begin[part + 1];
     for (;;) {
         __syncthreads();  // every wave's stores of the previous item are in L2
         if (threadIdx.x == 0) {
@@ -114,11 +127,11 @@ __global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs 
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __hip_atomic_fetch_add(a.counters + done_grid, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            item_sh = atomicAdd(a.cursor, 1);
+            item_sh = first + atomicAdd(a.cursors + part * kCursorStride, 1);
         }
         __syncthreads();
         const int it = __builtin_amdgcn_readfirstlane(item_sh);
-        if (it >= a.nitems) break;  // scalar branch: every wave leaves together
+        if (it >= last) break;  // scalar branch: every wave leaves together
         const int grid = __builtin_amdgcn_readfirstlane(a.items[it].grid);
         const int ipass = __builtin_amdgcn_readfirstlane(a.items[it].pass);
         const int iblk = __builtin_amdgcn_readfirstlane(a.items[it].blk);
