@@ -322,6 +322,18 @@ def bench_configs(a):
             % (name, f["GStencil/s"], f["k"], f["ms"], f["hbm_frac"], p["GStencil/s"], p["ms"], p["hbm_frac"]))
 
     entry("1d3p_262144_f64", W.case_1d3p(), "f64")
+    # the same launch-bound sweep replayed from a recorded HIP graph
+    case = W.case_1d3p()
+    x = torch.from_numpy(case.u0).cuda()
+    y = torch.empty_like(x)
+    for method in ("plain", "auto"):
+        plan = Plan(case.shape, 1, W.STAR, case.coeffs, W.BC_ZERO, "f64", method=method, graph=True)
+        ms = timed(lambda: plan.run(x, case.T, out=y), 3)
+        key = "plain" if method == "plain" else "fused"
+        out["1d3p_262144_f64"][key + "_graph"] = {"GStencil/s": x.numel() * case.T / ms / 1e6, "ms": ms}
+        log("1d3p graph replay (%s): %.3f ms, %.1f GStencil/s" % (key, ms, x.numel() * case.T / ms / 1e6))
+        plan.close()
+    del x, y
     for kind, nm in ((W.STAR, "2d5p"), (W.BOX, "2d9p")):
         entry(nm + "_8192_f32_periodic", W.case_2d(kind), "f32")
     for nm in ("3d7p", "3d13p", "3d27p"):

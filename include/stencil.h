@@ -87,6 +87,10 @@ typedef struct stencil_opts {
                      chunk count that minimises rounds of resident workgroups x
                      stream length, from the kernel's occupancy on the current
                      device) */
+    int graph;    /* nonzero: stencil_run records the launches of a (d_in, d_out, T)
+                     triple into a HIP graph on its first call and replays the graph
+                     while later calls repeat the triple (a new triple, autotuning or
+                     a device change re-records); for launch-bound small grids */
 } stencil_opts;
 
 /* What a plan resolved to (stencil_plan_info). */

@@ -43,7 +43,7 @@ class StencilError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("fused_k", ctypes.c_int), ("variant", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("chunk", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("chunk", ctypes.c_int), ("graph", ctypes.c_int)]
 
 
 class PlanDesc(ctypes.Structure):
@@ -131,11 +131,11 @@ def stencil_offsets(dim: int, radius: int, kind: int):
 
 def stencil_plan_create(shape, radius: int, kind: int, coeffs, bc: int, dtype: int,
                         method: int = METHOD_AUTO, fused_k: int = 0, variant: int = 0,
-                        autotune: bool = False, chunk: int = 0) -> int:
+                        autotune: bool = False, chunk: int = 0, graph: bool = False) -> int:
     dim = len(shape)
     sh = (ctypes.c_int64 * max(dim, 1))(*[int(s) for s in shape])
     c = (ctypes.c_double * len(coeffs))(*[float(v) for v in coeffs])
-    opts = Opts(method, fused_k, variant, 1 if autotune else 0, chunk)
+    opts = Opts(method, fused_k, variant, 1 if autotune else 0, chunk, 1 if graph else 0)
     out = ctypes.c_void_p()
     check(lib().stencil_plan_create(ctypes.byref(out), dim, sh, radius, kind, c, len(coeffs), bc,
                                     dtype, ctypes.byref(opts)), "stencil_plan_create")

@@ -300,6 +300,16 @@ int plan_prepare(stencil_plan *p, hipStream_t st) {
     return STENCIL_OK;
 }
 
+void plan_drop_graph(stencil_plan *p) {
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    p->graph_in = nullptr;
+    p->graph_out = nullptr;
+    p->graph_T = -1;
+}
+
 int plan_alloc_alias(stencil_plan *p) {
     if (p->scratch[1]) return STENCIL_OK;
     const size_t bytes = (size_t)p->points * elem_bytes(p->dtype);
@@ -396,6 +406,7 @@ static int autotune_impl(stencil_plan *p, hipStream_t st) {
         std::lock_guard<std::mutex> g(tune_mutex());
         auto it = tune_cache().find(sig);
         if (it != tune_cache().end()) {
+            plan_drop_graph(p);
             p->exec = it->second;
             p->tuned = 1;
             return STENCIL_OK;
@@ -435,6 +446,7 @@ static int autotune_impl(stencil_plan *p, hipStream_t st) {
             }
         }
     }
+    plan_drop_graph(p);
     p->exec = best;
     p->tuned = 1;
     std::lock_guard<std::mutex> g(tune_mutex());
@@ -539,12 +551,17 @@ int stencil_plan_create(stencil_plan **out, int dim, const int64_t *shape, int r
         for (int i = 0; i < dim; ++i) idx = idx * W + (p->offsets[j * dim + i] + radius);
         p->dense[idx] = coeffs[j];
     }
-    p->opts = opts ? *opts : stencil_opts{0, 0, 0, 0, 0};
+    p->opts = opts ? *opts : stencil_opts{0, 0, 0, 0, 0, 0};
     p->tuned = 0;
     p->device = -1;
     p->scratch[0] = p->scratch[1] = nullptr;
     p->d_off = nullptr;
     p->d_coef = nullptr;
+    p->graph = nullptr;
+    p->graph_exec = nullptr;
+    p->graph_in = nullptr;
+    p->graph_out = nullptr;
+    p->graph_T = -1;
     const int rc = resolve_exec(p);
     if (rc != STENCIL_OK) {
         delete p;
@@ -556,6 +573,7 @@ int stencil_plan_create(stencil_plan **out, int dim, const int64_t *shape, int r
 
 void stencil_plan_destroy(stencil_plan *p) {
     if (!p) return;
+    plan_drop_graph(p);
     if (p->scratch[0]) (void)hipFree(p->scratch[0]);
     if (p->scratch[1]) (void)hipFree(p->scratch[1]);
     if (p->d_off) (void)hipFree(p->d_off);
@@ -621,16 +639,54 @@ int stencil_run(stencil_plan *p, const void *d_in, void *d_out, int64_t T, void 
         rc = autotune_impl(p, st);
         if (rc != STENCIL_OK) return rc;
     }
-    const void *src = d_in;
     if (d_in == d_out && T > 0) {
         rc = plan_alloc_alias(p);
         if (rc != STENCIL_OK) return rc;
-        STN_HIP(hipMemcpyAsync(p->scratch[1], d_in, (size_t)p->points * elem_bytes(p->dtype),
-                               hipMemcpyDeviceToDevice, st));
-        src = p->scratch[1];
     }
-    const Exec ex = exec_for_ptrs(p, src, d_out);
-    return run_passes(p, ex, src, d_out, T, st);
+    // enqueue the whole sweep on `s` (the caller's stream, or a capture stream)
+    auto enqueue = [&](hipStream_t s) -> int {
+        const void *src = d_in;
+        if (d_in == d_out && T > 0) {
+            STN_HIP(hipMemcpyAsync(p->scratch[1], d_in, (size_t)p->points * elem_bytes(p->dtype),
+                                   hipMemcpyDeviceToDevice, s));
+            src = p->scratch[1];
+        }
+        const Exec ex = exec_for_ptrs(p, src, d_out);
+        return run_passes(p, ex, src, d_out, T, s);
+    };
+    if (!p->opts.graph || T == 0) return enqueue(st);
+    if (!(p->graph_exec && p->graph_in == d_in && p->graph_out == d_out && p->graph_T == T)) {
+        // record on a private stream: the caller's stream may be the legacy default
+        // stream, which cannot be captured; the launches depend on nothing else
+        plan_drop_graph(p);
+        hipStream_t cap = nullptr;
+        STN_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            return fail(STENCIL_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+        }
+        rc = enqueue(cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cap, &g);
+        (void)hipStreamDestroy(cap);
+        if (rc != STENCIL_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            p->graph_exec = nullptr;
+            return fail(STENCIL_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+        }
+        p->graph = g;
+        p->graph_in = d_in;
+        p->graph_out = d_out;
+        p->graph_T = T;
+    }
+    STN_HIP(hipGraphLaunch(p->graph_exec, st));
+    return STENCIL_OK;
 }
 
 int stencil_reduce(int dtype, const void *d_u, const void *d_ref, int64_t n, double *d_out, void *stream) {

@@ -54,11 +54,19 @@ struct stencil_plan {
     void *scratch[2];               // [0] ping-pong field, [1] copy of an aliased input
     int *d_off;                     // generic kernel tables
     void *d_coef;
+    // recorded launches of one (d_in, d_out, T) triple (opts.graph)
+    hipGraph_t graph;
+    hipGraphExec_t graph_exec;
+    const void *graph_in;
+    void *graph_out;
+    int64_t graph_T;
 };
 
 namespace stn {
 int plan_prepare(stencil_plan *p, hipStream_t st);
 int plan_alloc_alias(stencil_plan *p);
+// forget the recorded graph (the plan's execution choice or device changed)
+void plan_drop_graph(stencil_plan *p);
 // enqueue T steps with an explicit execution choice (no aliasing handling)
 int run_passes(stencil_plan *p, const Exec &ex, const void *src, void *dst, int64_t T, hipStream_t st);
 // ex with a lane width both pointers allow (falls back to the generic kernel)

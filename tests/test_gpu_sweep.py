@@ -239,3 +239,43 @@ def test_fused_plain_generic_bitwise_on_random_inputs(dim, r, kind, dt, bc):
     else:
         ref = outs["plain"].double()
         assert float((outs["fused"].double() - ref).abs().max() / ref.abs().max()) <= TOL[dt]
+
+
+@pytest.mark.parametrize("method", ["plain", "fused"])
+def test_graph_replays_match_eager_runs(method):
+    """Recorded launches (graph=True) replay the same sweep as eager runs, bit for
+    bit, on every replay, with eager work on the stream between replays; a new
+    (input, output, T) triple re-records; an aliased input still works."""
+    case = W.case_1d3p(seed=3, n=4099, T=37)
+    x = torch.from_numpy(case.u0).cuda()
+    eager = Plan(case.shape, 1, W.STAR, case.coeffs, W.BC_ZERO, "f64", method=method)
+    graph = Plan(case.shape, 1, W.STAR, case.coeffs, W.BC_ZERO, "f64", method=method, graph=True)
+    ref = eager.run(x, case.T)
+    y = torch.empty_like(x)
+    for rep in range(4):
+        y.fill_(float("nan"))
+        graph.run(x, case.T, out=y)
+        _ = eager.run(x, 5)                          # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), rep
+    ref2 = eager.run(x, 12)
+    graph.run(x, 12, out=y)                          # new triple: re-recorded
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref2)
+    z = x.clone()
+    graph.run(z, case.T, out=z)                      # aliased input and output
+    torch.cuda.synchronize()
+    assert torch.equal(z, ref)
+    for T, r in ((case.T, ref), (12, ref2)):
+        want = oracle.run(case.u0, case.coeffs, T, r=1, kind=W.STAR, bc=W.BC_ZERO)
+        assert rel_err(r.cpu().numpy(), want) <= 1e-12
+    # a 3D fused plan records its passes the same way
+    c3 = W.case_3d("3d7p", seed=1, n=40, T=11)
+    x3 = torch.from_numpy(c3.u0).float().cuda()
+    g3 = Plan(c3.shape, 1, W.STAR, c3.coeffs, W.BC_ZERO, "f32", method="fused", graph=True)
+    e3 = Plan(c3.shape, 1, W.STAR, c3.coeffs, W.BC_ZERO, "f32", method="fused")
+    y3 = torch.empty_like(x3)
+    for rep in range(3):
+        g3.run(x3, c3.T, out=y3)
+        torch.cuda.synchronize()
+        assert torch.equal(y3, e3.run(x3, c3.T)), rep
