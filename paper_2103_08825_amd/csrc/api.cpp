@@ -152,8 +152,8 @@ struct Choice {
 };
 static const Choice kChoices[] = {
     // 3D FP32: 7-point, 27-point, 13-point
-    {3, 1, STENCIL_STAR, 1, 5, 5, 0, 3, 0}, {3, 1, STENCIL_BOX, 1, 4, 3, 128, 4, 32},
-    {3, 2, STENCIL_STAR, 1, 4, 2, 64, 4, 0},
+    {3, 1, STENCIL_STAR, 1, 5, 5, 0, 3, 0}, {3, 1, STENCIL_BOX, 1, 5, 3, 0, 5, 0},
+    {3, 2, STENCIL_STAR, 1, 4, 2, 64, 5, 0},
     // 3D 16-bit storage
     {3, 1, STENCIL_STAR, 2, 5, 6, 0, 5, 0}, {3, 1, STENCIL_BOX, 2, 4, 3, 64, 4, 0},
     {3, 2, STENCIL_STAR, 2, 4, 2, 64, 1, 64},
@@ -192,13 +192,17 @@ static int resolve_exec(stencil_plan *p) {
             return fail(STENCIL_E_INVALID, "variant %d needs the last extent to be a multiple of %d",
                         variant, v.vx);
     } else {
-        variant = default_variant(p, 1);
+        // a requested depth narrows the choice to variants compiled that deep
+        const int need_k = method == STENCIL_METHOD_FUSED && o.fused_k > 0 ? o.fused_k : 1;
+        variant = default_variant(p, need_k);
+        if (variant == 0) variant = default_variant(p, 1);  // reported as too deep below
     }
     const Choice *mc = measured_choice(p);
     int chunk = o.chunk;
     if (mc && o.variant == 0) {
         const int mv = method == STENCIL_METHOD_PLAIN ? mc->pvariant : mc->variant;
-        if (variant_fits_shape(p, mv) && max_k_of(p, mv) >= 1) {
+        const int need_k = method == STENCIL_METHOD_FUSED && o.fused_k > 0 ? o.fused_k : 1;
+        if (variant_fits_shape(p, mv) && max_k_of(p, mv) >= need_k) {
             variant = mv;
             if (o.chunk == 0) chunk = method == STENCIL_METHOD_PLAIN ? mc->pchunk : mc->chunk;
         }

@@ -169,3 +169,15 @@ def test_error_text_is_thread_local(L):
     t.start()
     t.join()
     assert main_msg != "" and seen == [""]
+
+
+def test_requested_depth_picks_a_variant_compiled_that_deep(L):
+    # the measured default tile of the 27-point FP32 box is compiled up to k = 3;
+    # asking for k = 4 without a variant must choose a tile compiled that deep
+    rc, h = _create(L, (64, 64, 64), 1, 1, [1 / 27] * 27, 0, _lib.F32, method=_lib.METHOD_FUSED, fused_k=4)
+    assert rc == 0, _lib.last_error()
+    info = _lib.stencil_plan_info(h)
+    assert info["fused_k"] == 4 and info["variant"] != 0
+    _lib.stencil_plan_destroy(h)
+    rc, h = _create(L, (64, 64, 64), 1, 1, [1 / 27] * 27, 0, _lib.F32, method=_lib.METHOD_FUSED, fused_k=99)
+    assert rc == _lib.STENCIL_E_UNSUPPORTED and "exceeds" in _lib.last_error()
