@@ -152,7 +152,7 @@ struct Choice {
 };
 static const Choice kChoices[] = {
     // 3D FP32: 7-point, 27-point, 13-point
-    {3, 1, STENCIL_STAR, 1, 5, 5, 0, 3, 0}, {3, 1, STENCIL_BOX, 1, 5, 3, 0, 5, 0},
+    {3, 1, STENCIL_STAR, 1, 5, 5, 0, 3, 8}, {3, 1, STENCIL_BOX, 1, 5, 3, 0, 5, 0},
     {3, 2, STENCIL_STAR, 1, 4, 2, 64, 5, 0},
     // 3D 16-bit storage
     {3, 1, STENCIL_STAR, 2, 5, 6, 0, 5, 0}, {3, 1, STENCIL_BOX, 2, 4, 3, 64, 4, 0},
