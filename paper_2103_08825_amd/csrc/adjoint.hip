@@ -224,7 +224,7 @@ static int one_step(stencil_plan *p, const Exec &ex, const std::vector<double> &
     return STENCIL_OK;
 }
 
-static int adjoint_impl(stencil_plan *p, const Exec &ex, const void *d_u0, const void *d_gT, int64_t T,
+static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const void *d_u0, const void *d_gT, int64_t T,
                         int64_t C, void *d_gu, double *d_gc, hipStream_t st) {
     const size_t field = (size_t)p->points * elem_bytes(p->dtype);
     if (T == 0) {
@@ -279,7 +279,7 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const void *d_u0, const
             return t == tb ? ck(s) : static_cast<const void *>(seg_base + (size_t)(t - tb - 1) * field);
         };
         for (int64_t t = tb + 1; t < te && rc == STENCIL_OK; ++t)
-            rc = one_step(p, ex, p->dense, p->d_off, p->d_coef, state(t - 1), const_cast<void *>(state(t)), st);
+            rc = one_step(p, ex1, p->dense, p->d_off, p->d_coef, state(t - 1), const_cast<void *>(state(t)), st);
         if (rc != STENCIL_OK) return done(rc);
         for (int64_t t = te - 1; t >= tb; --t) {
             e = p->dtype == STENCIL_F64 ? launch_grad<double>(p, lam, state(t), off3, part, st)
@@ -288,7 +288,7 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const void *d_u0, const
             void *out = (t == 0) ? d_gu : lam_buf[flip];
             // the generic fallback needs mirrored weights in compute precision on the device:
             // the plan's d_coef holds the weights in canonical order, which pair with d_offm
-            rc = one_step(p, ex, dense_m, d_offm, p->d_coef, lam, out, st);
+            rc = one_step(p, ex1, dense_m, d_offm, p->d_coef, lam, out, st);
             if (rc != STENCIL_OK) return done(rc);
             lam = out;
             flip ^= 1;
@@ -322,6 +322,7 @@ extern "C" int stencil_adjoint(stencil_plan *p, const void *d_u0, const void *d_
     // the workspace is 256-byte aligned; the caller's three buffers decide the lane
     // width (alignments are powers of two, so OR-ing two addresses keeps the weaker)
     const void *either = reinterpret_cast<const void *>((uintptr_t)d_u0 | (uintptr_t)d_gT);
-    const Exec ex = exec_for_ptrs(p, either, d_grad_u0);
-    return adjoint_impl(p, ex, d_u0, d_gT, T, checkpoint_every, d_grad_u0, d_grad_coeffs, st);
+    const Exec ex = exec_for_ptrs(p, either, d_grad_u0);                     // checkpoint passes
+    const Exec ex1 = exec_for_ptrs(p, one_step_exec(p), either, d_grad_u0);  // single steps
+    return adjoint_impl(p, ex, ex1, d_u0, d_gT, T, checkpoint_every, d_grad_u0, d_grad_coeffs, st);
 }

@@ -359,9 +359,26 @@ int run_passes(stencil_plan *p, const Exec &ex, const void *src, void *dst, int6
     return STENCIL_OK;
 }
 
-// choose an execution whose lane width suits both pointers
-Exec exec_for_ptrs(const stencil_plan *p, const void *a, const void *b) {
+// one step per launch for this plan: the measured plain choice, else the plan's
+// own tile at k = 1 (the generic kernel stays generic)
+Exec one_step_exec(const stencil_plan *p) {
     Exec ex = p->exec;
+    if (ex.method == STENCIL_METHOD_GENERIC) return ex;
+    ex.method = STENCIL_METHOD_PLAIN;
+    ex.k = 1;
+    ex.chunk = 0;
+    const Choice *mc = measured_choice(p);
+    if (mc && variant_fits_shape(p, mc->pvariant) && max_k_of(p, mc->pvariant) >= 1) {
+        ex.variant = mc->pvariant;
+        ex.chunk = mc->pchunk;
+    }
+    return ex;
+}
+
+// choose an execution whose lane width suits both pointers
+Exec exec_for_ptrs(const stencil_plan *p, const void *a, const void *b) { return exec_for_ptrs(p, p->exec, a, b); }
+
+Exec exec_for_ptrs(const stencil_plan *p, Exec ex, const void *a, const void *b) {
     if (ex.method == STENCIL_METHOD_GENERIC || variant_fits_ptr(p, ex.variant, a, b)) return ex;
     for (int v = 1; v <= num_variants_of(p->dim); ++v) {
         if (variant_fits_ptr(p, v, a, b) && max_k_of(p, v) >= ex.k) {

@@ -71,6 +71,10 @@ void plan_drop_graph(stencil_plan *p);
 int run_passes(stencil_plan *p, const Exec &ex, const void *src, void *dst, int64_t T, hipStream_t st);
 // ex with a lane width both pointers allow (falls back to the generic kernel)
 Exec exec_for_ptrs(const stencil_plan *p, const void *a, const void *b);
+// the same starting from `ex` instead of the plan's execution
+Exec exec_for_ptrs(const stencil_plan *p, Exec ex, const void *a, const void *b);
+// one step per launch (the measured plain choice where there is one)
+Exec one_step_exec(const stencil_plan *p);
 // launcher of one pass of k steps under ex (nullptr if none)
 SweepLauncher pass_launcher(const stencil_plan *p, const Exec &ex, int k);
 hipError_t launch_reduce(int dtype, const void *u, const void *ref, int64_t n, double *part,
