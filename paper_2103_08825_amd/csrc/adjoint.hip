@@ -44,6 +44,27 @@ template <typename S> __device__ __forceinline__ double load_f64(rsrc_t r, int i
     return (double)to_compute(__builtin_bit_cast(S, buf_load<sizeof(S)>(r, (uint32_t)idx * (uint32_t)sizeof(S))));
 }
 
+// Fold a workgroup's per-lane sums in a fixed order and add them to the
+// workgroup's own slots part[block][j0 + q], q < nj.
+template <int P>
+__device__ __forceinline__ void fold_block(const double (&acc)[P], int j0, int nj, int npts, double *part) {
+    __shared__ double sh[kGradThreads / 64][P];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) sh[w][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nj) {
+        double v = sh[0][threadIdx.x];
+        for (int k = 1; k < kGradThreads / 64; ++k) v += sh[k][threadIdx.x];
+        part[(int64_t)blockIdx.x * npts + j0 + threadIdx.x] += v;
+    }
+}
+
 // P: accumulators compiled (8 covers the 1D-3D order-1 stars and 2D boxes; 32 the
 // rest).  BUF: the field is below 2 GiB, so the row-interior path addresses it
 // with 32-bit offsets into a buffer resource (one register per address, which
@@ -145,22 +166,268 @@ __global__ void __launch_bounds__(kGradThreads)
             }
         }
     }
-    // fold the block in a fixed order and add to this block's own slots
-    __shared__ double sh[kGradThreads / 64][P];
-    const int w = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        double v = acc[q];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) sh[w][q] = v;
+    fold_block<P>(acc, j0, nj, npts, part);
+}
+
+// Tiled gradient for 2D and 3D grids.  A workgroup takes tiles of 64 rows of 64
+// points (3D: 8 x 8 rows along axes 0 and 1; 2D: 64 rows along axis 0), stages
+// u over the tile and its halo of RH points per axis in LDS (rows of 64 + 2 RH,
+// loaded coalesced, with the boundary rule applied once per element), and
+// reads lambda for its own points straight into registers.  Each lane then
+// sums lambda[x] u[x + o_q] over its 16 points for every offset from LDS, so u
+// is read from memory about once per tile instead of once per offset.  Tiles
+// are split into 8 contiguous ranges, range x served by the workgroups that
+// are dispatched to XCD x, so neighbouring tiles share their halo rows in one
+// L2.
+constexpr int kTileRows = 64;
+constexpr int kTilePts = kTileRows / (kGradThreads / 64);  // points per lane and tile
+
+struct TileOffsets {
+    int lds[kGradMaxP];  // (o0 H1 + o1) H2 + o2 in the halo tile's layout
+};
+
+template <int T1, int RH> struct TileShape {
+    static constexpr int T0 = kTileRows / T1;
+    static constexpr int R0 = RH, R1 = T1 > 1 ? RH : 0, R2 = RH;
+    static constexpr int H0 = T0 + 2 * R0, H1 = T1 + 2 * R1, H2 = 64 + 2 * R2;
+};
+
+// index along one axis after the boundary rule, for |y - clamp(y)| <= n: in
+// range, wrapped once (periodic), or -1 (zero halo, or farther out than any
+// offset reaches from a point of the grid: such elements are never used)
+template <typename I> __device__ __forceinline__ I bound_index(I y, I n, bool periodic) {
+    const I w = y < 0 ? y + n : (y >= n ? y - n : y);
+    const bool ok = (y >= 0 && y < n) || (periodic && w >= 0 && w < n);
+    return ok ? w : (I)-1;
+}
+
+// Element reads of a field as row offset + column offset.  BUF: byte offsets
+// into a buffer resource of at most 2^31 - 1 bytes; an invalid row adds 2^31
+// and an invalid column 2^31 - 1, so any invalid part puts the sum (no wrap
+// below 2^32) past the resource's end, where the load returns 0.  Otherwise:
+// 64-bit element offsets, -1 for invalid, and a select.
+template <typename S, bool BUF> struct FieldReader;
+template <typename S> struct FieldReader<S, true> {
+    using I = int;
+    using Off = uint32_t;
+    rsrc_t r;
+    __device__ FieldReader(const S *p, int64_t n) : r(make_rsrc(p, (uint32_t)(n * (int64_t)sizeof(S)))) {}
+    static __device__ __forceinline__ Off row(I elem, bool ok) {
+        return ok ? (uint32_t)elem * (uint32_t)sizeof(S) : 0x80000000u;
     }
-    __syncthreads();
-    if (threadIdx.x < nj) {
-        double v = sh[0][threadIdx.x];
-        for (int k = 1; k < kGradThreads / 64; ++k) v += sh[k][threadIdx.x];
-        part[(int64_t)blockIdx.x * npts + j0 + threadIdx.x] += v;
+    static __device__ __forceinline__ Off col(I elem, bool ok) {
+        return ok ? (uint32_t)elem * (uint32_t)sizeof(S) : 0x7fffffffu;
     }
+    __device__ __forceinline__ typename ComputeOf<S>::type get(Off row, Off col) const {
+        return to_compute(__builtin_bit_cast(S, buf_load<sizeof(S)>(r, row + col)));
+    }
+};
+template <typename S> struct FieldReader<S, false> {
+    using I = int64_t;
+    using Off = int64_t;
+    const S *p;
+    __device__ FieldReader(const S *q, int64_t) : p(q) {}
+    static __device__ __forceinline__ Off row(I elem, bool ok) { return ok ? elem : (Off)-1; }
+    static __device__ __forceinline__ Off col(I elem, bool ok) { return ok ? elem : (Off)-1; }
+    __device__ __forceinline__ typename ComputeOf<S>::type get(Off row, Off col) const {
+        using C = typename ComputeOf<S>::type;
+        const bool ok = row >= 0 && col >= 0;
+        const C v = to_compute(p[ok ? row + col : 0]);
+        return ok ? v : (C)0;
+    }
+};
+
+template <typename S, int P, int T1, int RH, bool BUF>
+__global__ void __launch_bounds__(kGradThreads)
+    coeff_grad_tiled(const S *__restrict__ lam, const S *__restrict__ u, int64_t n0_, int64_t n1_, int64_t n2_,
+                     int bc, const TileOffsets g, int j0, int nj, int npts, double *__restrict__ part) {
+    using C = typename ComputeOf<S>::type;
+    using TS = TileShape<T1, RH>;
+    using RD = FieldReader<S, BUF>;
+    using I = typename RD::I;
+    using Off = typename RD::Off;
+    constexpr int T0 = TS::T0, R0 = TS::R0, R1 = TS::R1, R2 = TS::R2, H1 = TS::H1, H2 = TS::H2;
+    constexpr int NROW = TS::H0 * H1;  // halo-tile rows of H2 elements
+    __shared__ C tile[NROW * H2];
+    // row offsets of the tile's u rows [0, NROW) and lambda rows [NROW, NROW + 64)
+    __shared__ Off rowtab[NROW + kTileRows];
+    static_assert(NROW + kTileRows <= kGradThreads, "one row-table entry per thread");
+    double acc[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc[q] = 0.0;
+    const bool periodic = bc == 1;
+    const I n0 = (I)n0_, n1 = (I)n1_, n2 = (I)n2_, n12 = n1 * n2;
+    const RD rl(lam, n0_ * n1_ * n2_), ru(u, n0_ * n1_ * n2_);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const I nt0 = (n0 + T0 - 1) / T0, nt1 = (n1 + T1 - 1) / T1, nt2 = (n2 + 63) / 64;
+    const I ntile = nt0 * nt1 * nt2;
+    const int xcd = blockIdx.x % 8, per = gridDim.x / 8;
+    const I lo = (I)((int64_t)ntile * xcd / 8), hi = (I)((int64_t)ntile * (xcd + 1) / 8);
+    // this lane's first point in the halo tile; point i (row wv + 4 i) adds
+    // the constant step below
+    const int base = ((R0 + (T1 > 1 ? 0 : wv)) * H1 + R1 + (T1 > 1 ? wv : 0)) * H2 + R2 + lane;
+    auto step = [](int i) { return T1 > 1 ? (i >> 1) * H1 * H2 + (i & 1) * 4 * H2 : 4 * i * H2; };
+    for (I tt = lo + blockIdx.x / 8; tt < hi; tt += per) {
+        const I b2 = tt % nt2, b01 = tt / nt2;
+        const I c0 = (b01 / nt1) * T0, c1 = (b01 % nt1) * T1, c2 = b2 * 64;
+        {
+            // one row-table entry per thread, axis indices after the boundary rule
+            const int e = threadIdx.x;
+            if (e < NROW) {
+                const I y0 = bound_index<I>(c0 + e / H1 - R0, n0, periodic);
+                const I y1 = bound_index<I>(c1 + e % H1 - R1, n1, periodic);
+                const bool ok = y0 >= 0 && y1 >= 0;
+                rowtab[e] = RD::row(ok ? y0 * n12 + y1 * n2 : 0, ok);
+            } else if (e < NROW + kTileRows) {
+                const int rr = e - NROW;
+                const I x0 = c0 + rr / T1, x1 = c1 + rr % T1;
+                const bool ok = x0 < n0 && x1 < n1;
+                rowtab[e] = RD::row(ok ? x0 * n12 + x1 * n2 : 0, ok);
+            }
+        }
+        // the table is complete, and every wave is done with the previous tile
+        __syncthreads();
+        // all loads of the tile issue before the first wait; invalid elements read 0
+        const I x2 = c2 + lane;
+        const I m2 = bound_index<I>(x2, n2, periodic);
+        const Off ucol = RD::col(m2, m2 >= 0), lcol = RD::col(x2, x2 < n2);
+        double l[kTilePts];
+#pragma unroll
+        for (int i = 0; i < kTilePts; ++i) l[i] = (double)rl.get(rowtab[NROW + wv + 4 * i], lcol);
+        constexpr int NIT = (NROW + 3) / 4;
+        C uv[NIT];
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) {
+            const int hr = k * 4 + 3 < NROW ? k * 4 + wv : min(k * 4 + wv, NROW - 1);
+            uv[k] = ru.get(rowtab[hr], ucol);
+        }
+        // halo columns: R2 on each side of every row
+        constexpr int NHALO = NROW * 2 * R2;
+        constexpr int NHIT = (NHALO + kGradThreads - 1) / kGradThreads;
+        C hv[NHIT];
+#pragma unroll
+        for (int k = 0; k < NHIT; ++k) {
+            const int e0 = k * kGradThreads + (int)threadIdx.x;
+            const int e = e0 < NHALO ? e0 : NHALO - 1;
+            const int hr = e / (2 * R2), c = e % (2 * R2);
+            const I y2 = bound_index<I>(c2 + (c < R2 ? c : 64 + c) - R2, n2, periodic);
+            hv[k] = ru.get(rowtab[hr], RD::col(y2, y2 >= 0));
+        }
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) {
+            const int hr = k * 4 + wv;
+            if (hr < NROW) tile[hr * H2 + R2 + lane] = uv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NHIT; ++k) {
+            const int e = k * kGradThreads + (int)threadIdx.x;
+            if (e < NHALO) {
+                const int hr = e / (2 * R2), c = e % (2 * R2);
+                tile[hr * H2 + (c < R2 ? c : 64 + c)] = hv[k];
+            }
+        }
+        __syncthreads();  // the tile is complete
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            if (q < nj) {  // uniform
+                const C *t = tile + base + g.lds[q];
+#pragma unroll
+                for (int i = 0; i < kTilePts; ++i) acc[q] = fma(l[i], (double)t[step(i)], acc[q]);
+            }
+        }
+    }
+    fold_block<P>(acc, j0, nj, npts, part);
+}
+
+// Tiled gradient for 1D grids: tiles of 64 x 64 consecutive points plus RH on
+// each side in LDS; lane l of wave w takes points 64 (w + 4 i) + l.
+template <typename S, int P, int RH, bool BUF>
+__global__ void __launch_bounds__(kGradThreads)
+    coeff_grad_line(const S *__restrict__ lam, const S *__restrict__ u, int64_t n_, int bc, const TileOffsets g,
+                    int j0, int nj, int npts, double *__restrict__ part) {
+    using C = typename ComputeOf<S>::type;
+    using RD = FieldReader<S, BUF>;
+    using I = typename RD::I;
+    constexpr int TP = kTileRows * 64;  // points per tile
+    __shared__ C tile[TP + 2 * RH];
+    double acc[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc[q] = 0.0;
+    const bool periodic = bc == 1;
+    const I n = (I)n_;
+    const RD rl(lam, n_), ru(u, n_);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const I ntile = (n + TP - 1) / TP;
+    const int xcd = blockIdx.x % 8, per = gridDim.x / 8;
+    const I lo = (I)((int64_t)ntile * xcd / 8), hi = (I)((int64_t)ntile * (xcd + 1) / 8);
+    const int base = RH + 64 * wv + lane;
+    for (I tt = lo + blockIdx.x / 8; tt < hi; tt += per) {
+        const I c = tt * TP;
+        // all loads of the tile issue before the first wait; invalid elements read 0
+        double l[kTilePts];
+        C uv[kTilePts];
+#pragma unroll
+        for (int i = 0; i < kTilePts; ++i) {
+            const I x = c + base - RH + 256 * i;
+            const I m = bound_index<I>(x, n, periodic);
+            l[i] = (double)rl.get(RD::row(0, true), RD::col(x, x < n));
+            uv[i] = ru.get(RD::row(0, true), RD::col(m, m >= 0));
+        }
+        C hv = (C)0;
+        const int he = threadIdx.x < RH ? (int)threadIdx.x : TP + (int)threadIdx.x;  // halo slot (first 2 RH threads)
+        if (threadIdx.x < 2 * RH) {
+            const I y = bound_index<I>(c + he - RH, n, periodic);
+            hv = ru.get(RD::row(0, true), RD::col(y, y >= 0));
+        }
+        __syncthreads();  // every wave is done with the previous tile
+#pragma unroll
+        for (int i = 0; i < kTilePts; ++i) tile[base + 256 * i] = uv[i];
+        if (threadIdx.x < 2 * RH) tile[he] = hv;
+        __syncthreads();  // the tile is complete
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            if (q < nj) {  // uniform
+                const C *t = tile + base + g.lds[q];
+#pragma unroll
+                for (int i = 0; i < kTilePts; ++i) acc[q] = fma(l[i], (double)t[256 * i], acc[q]);
+            }
+        }
+    }
+    fold_block<P>(acc, j0, nj, npts, part);
+}
+
+template <typename S, int RH>
+static void launch_line(const stencil_plan *p, const S *lam, const S *u, const TileOffsets &g, int j0, int nj,
+                        double *part, hipStream_t st) {
+    const int64_t ntile = (p->n2 + kTileRows * 64 - 1) / (kTileRows * 64);
+    const int grid = (int)std::min<int64_t>(kGradBlocks, (ntile + 7) / 8 * 8);
+    const bool buf = p->points * (int64_t)sizeof(S) < ((int64_t)1 << 31);
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kGradThreads), 0, st, lam, u, p->n2, p->bc, g, j0, nj, p->npts,
+                           part);
+    };
+    buf ? go(coeff_grad_line<S, 8, RH, true>) : go(coeff_grad_line<S, 8, RH, false>);
+}
+
+template <typename S, int T1, int RH>
+static void launch_tiled(const stencil_plan *p, const S *lam, const S *u, const TileOffsets &g, int j0, int nj,
+                         double *part, hipStream_t st) {
+    using TS = TileShape<T1, RH>;
+    const int64_t ntile = ((p->n0 + TS::T0 - 1) / TS::T0) * ((p->n1 + T1 - 1) / T1) * ((p->n2 + 63) / 64);
+    // a multiple of 8 (one share per XCD), at most the partial slots there are
+    const int grid = (int)std::min<int64_t>(kGradBlocks, (ntile + 7) / 8 * 8);
+    // 32-bit indices when every element offset (and byte offset) fits
+    const bool buf = p->points * (int64_t)sizeof(S) < ((int64_t)1 << 31);
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kGradThreads), 0, st, lam, u, p->n0, p->n1, p->n2, p->bc, g, j0,
+                           nj, p->npts, part);
+    };
+    if (nj <= 8)
+        buf ? go(coeff_grad_tiled<S, 8, T1, RH, true>) : go(coeff_grad_tiled<S, 8, T1, RH, false>);
+    else
+        buf ? go(coeff_grad_tiled<S, kGradMaxP, T1, RH, true>) : go(coeff_grad_tiled<S, kGradMaxP, T1, RH, false>);
 }
 
 // out[j] = sum over blocks of part[block][j], one workgroup per j, fixed order
@@ -196,10 +463,35 @@ static hipError_t launch_grad(const stencil_plan *p, const void *lam, const void
                 g.reach[i] = std::max(g.reach[i], std::abs(o[i]));
             }
         }
+        const S *l = static_cast<const S *>(lam), *v = static_cast<const S *>(u);
+        // offsets of at most 2 per axis: the LDS-tiled kernels
+        const int rh = std::max(g.reach[0], std::max(g.reach[1], g.reach[2]));
+        // (a single wrap per axis must reach: every axis at least as long as its reach)
+        const bool fits = p->n0 >= g.reach[0] && p->n1 >= g.reach[1] && p->n2 >= g.reach[2];
+        if (p->dim == 1 && rh <= 2 && fits && nj <= 8) {
+            TileOffsets to{};
+            for (int q = 0; q < nj; ++q) to.lds[q] = g.ax[q][2];
+            rh <= 1 ? launch_line<S, 1>(p, l, v, to, j0, nj, part, st) : launch_line<S, 2>(p, l, v, to, j0, nj, part, st);
+            continue;
+        }
+        if (p->dim >= 2 && rh <= 2 && fits) {
+            TileOffsets to{};
+            const bool d3 = p->dim == 3;
+            const int R = rh <= 1 ? 1 : 2;
+            const int H1 = d3 ? 8 + 2 * R : 1, H2 = 64 + 2 * R;
+            for (int q = 0; q < nj; ++q) to.lds[q] = (g.ax[q][0] * H1 + g.ax[q][1]) * H2 + g.ax[q][2];
+            if (d3)
+                R == 1 ? launch_tiled<S, 8, 1>(p, l, v, to, j0, nj, part, st)
+                       : launch_tiled<S, 8, 2>(p, l, v, to, j0, nj, part, st);
+            else
+                R == 1 ? launch_tiled<S, 1, 1>(p, l, v, to, j0, nj, part, st)
+                       : launch_tiled<S, 1, 2>(p, l, v, to, j0, nj, part, st);
+            continue;
+        }
         const bool buf = p->points * (int64_t)sizeof(S) < ((int64_t)1 << 31);
         auto go = [&](auto kernel) {
-            hipLaunchKernelGGL(kernel, dim3(kGradBlocks), dim3(kGradThreads), 0, st, static_cast<const S *>(lam),
-                               static_cast<const S *>(u), p->n0, p->n1, p->n2, p->bc, g, j0, nj, p->npts, part);
+            hipLaunchKernelGGL(kernel, dim3(kGradBlocks), dim3(kGradThreads), 0, st, l, v, p->n0, p->n1, p->n2, p->bc,
+                               g, j0, nj, p->npts, part);
         };
         if (nj <= 8)
             buf ? go(coeff_grad_kernel<S, 8, true>) : go(coeff_grad_kernel<S, 8, false>);

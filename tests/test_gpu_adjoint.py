@@ -52,6 +52,51 @@ def test_adjoint_matches_oracle(dim, r, kind, bc, dt):
     assert e_u <= TOL[dt] and e_c <= TOL[dt], (e_u, e_c)
 
 
+# ragged tiles along every axis (the coefficient-gradient kernels take tiles of
+# 8 x 8 x 64, 64 x 64 and 4096 points), axes shorter than a tile, and an axis
+# shorter than the stencil's reach (n0 = 1 with r = 2: the untiled kernel)
+@pytest.mark.parametrize("dim,r,kind,shape", [(3, 1, 1, (9, 17, 133)), (3, 2, 0, (13, 6, 70)),
+                                              (3, 1, 0, (10, 10, 5)), (3, 2, 0, (1, 12, 40)),
+                                              (2, 2, 1, (70, 150)), (2, 1, 0, (3, 200)),
+                                              (1, 2, 0, (9000,)), (1, 1, 0, (5,))])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_adjoint_ragged_tiles_match_oracle(dim, r, kind, shape, bc, dt):
+    _, c, c_ex, x, u_ex, y = _setup(dim, r, kind, bc, dt, seed=7 + dim + r, shape=shape)
+    T, ckpt = 5, 2
+    plan = Plan(shape, r, kind, c, bc, dt)
+    say("adjoint ragged %s r=%d kind=%d bc=%d %s" % (shape, r, kind, bc, dt))
+    g = (plan.run(x, T) - torch.from_numpy(y).to(x.dtype).cuda()).contiguous()
+    gu, gc = plan.adjoint(x, g, T, ckpt)
+    torch.cuda.synchronize()
+    ref_u, ref_c = oracle.adjoint(u_ex, c_ex, g.double().cpu().numpy(), T, r=r, kind=kind, bc=bc,
+                                  ckpt=ckpt)
+    e_u = rel_err(gu.double().cpu().numpy(), ref_u)
+    e_c = rel_err(gc.cpu().numpy(), ref_c)
+    assert e_u <= TOL[dt] and e_c <= TOL[dt], (e_u, e_c)
+
+
+def test_adjoint_field_beyond_2gib_matches_oracle():
+    """A 2.15 GB FP32 field: the kernels address it with 64-bit offsets."""
+    shape = (512, 1024, 1025)
+    _, c, c_ex, x, u_ex, y = _setup(3, 1, 0, 1, "f32", seed=31, shape=shape)
+    assert x.numel() * 4 >= 1 << 31
+    plan = Plan(shape, 1, 0, c, 1, "f32")
+    say("adjoint beyond 2 GiB %s" % (shape,))
+    g = torch.from_numpy(y).float().cuda()
+    del y
+    T = 2
+    gu, gc = plan.adjoint(x, g, T, 1)
+    torch.cuda.synchronize()
+    g64 = g.double().cpu().numpy()
+    del g
+    ref_u, ref_c = oracle.adjoint(u_ex, c_ex, g64, T, r=1, kind=0, bc=1, ckpt=1)
+    del g64
+    e_c = rel_err(gc.cpu().numpy(), ref_c)
+    e_u = rel_err(gu.double().cpu().numpy(), ref_u)
+    assert e_u <= TOL["f32"] and e_c <= TOL["f32"], (e_u, e_c)
+
+
 def test_adjoint_checkpoint_interval_invariance_bitwise():
     """The recomputed states and the partial sums do not depend on the interval."""
     shape, c, c_ex, x, u_ex, y = _setup(3, 1, 0, 0, "f32", seed=4)
