@@ -6,9 +6,10 @@
 // and dL/du_0 = lambda_0.  The mirrored stencil is the plan's own stencil with
 // the weight of offset o moved to -o, run by the same sweep kernels.  Forward
 // states come from checkpoints every `ckpt` steps (the fused sweep) and are
-// rebuilt one step at a time per segment.  The coefficient sums run in a
-// kernel whose workgroups walk row segments and keep their own FP64 partial
-// slots across all steps (fixed order, no atomics); one fold at the end.
+// rebuilt one step at a time per segment.  The coefficient sums run in
+// LDS-tiled kernels (an untiled kernel covers grids with an axis shorter than
+// the offsets' reach) whose workgroups keep their own FP64 partial slots
+// across all steps (fixed order, no atomics); one fold at the end.
 #include <algorithm>
 #include <cstdlib>
 #include <vector>
@@ -23,26 +24,18 @@ constexpr int kGradBlocks = 2048;
 constexpr int kGradThreads = 256;
 constexpr int kGradMaxP = 32;  // offsets per pass of the gradient kernel
 
-// offsets of one gradient pass in the 3-axis view: per-axis components and the
-// linear element offset (o0 n1 + o1) n2 + o2, uniform for every thread
+// offsets of one gradient pass in the 3-axis view, uniform for every thread
 struct GradOffsets {
-    int64_t lin[kGradMaxP];
     int ax[kGradMaxP][3];
     int reach[3];  // largest |component| per axis over the pass
 };
 
-// Each wave takes tasks of kGradU x 64 consecutive points of one grid row
-// (row = (x0, x1)); lane l handles points c0 + l + 64 i, i < kGradU, so every
-// load is coalesced and the kGradU x (1 + nj) loads of a task are independent.
-// Tasks in rows away from the faces of axes 0 and 1 read u[p + lin[j]] with a
-// row-end correction (a uniform branch); the few others apply the boundary rule
-// per point and offset.
+// Untiled kernel, for grids with an axis shorter than the offsets' reach (where
+// one wrap per axis is not enough): each wave takes tasks of kGradU x 64
+// consecutive points of one grid row (row = (x0, x1)); lane l handles points
+// c0 + l + 64 i, i < kGradU, and applies the boundary rule per point and offset.
 constexpr int kGradU = 4;
 constexpr int kGradTask = 64 * kGradU;
-
-template <typename S> __device__ __forceinline__ double load_f64(rsrc_t r, int idx) {
-    return (double)to_compute(__builtin_bit_cast(S, buf_load<sizeof(S)>(r, (uint32_t)idx * (uint32_t)sizeof(S))));
-}
 
 // Fold a workgroup's per-lane sums in a fixed order and add them to the
 // workgroup's own slots part[block][j0 + q], q < nj.
@@ -65,11 +58,8 @@ __device__ __forceinline__ void fold_block(const double (&acc)[P], int j0, int n
     }
 }
 
-// P: accumulators compiled (8 covers the 1D-3D order-1 stars and 2D boxes; 32 the
-// rest).  BUF: the field is below 2 GiB, so the row-interior path addresses it
-// with 32-bit offsets into a buffer resource (one register per address, which
-// lets the compiler keep all of a task's loads in flight).
-template <typename S, int P, bool BUF>
+// P: accumulators compiled (8 covers the 1D-3D order-1 stars and 2D boxes; 32 the rest)
+template <typename S, int P>
 __global__ void __launch_bounds__(kGradThreads)
     coeff_grad_kernel(const S *__restrict__ lam, const S *__restrict__ u, int64_t n0, int64_t n1, int64_t n2,
                       int bc, const GradOffsets g, int j0, int nj, int npts, double *__restrict__ part) {
@@ -77,7 +67,6 @@ __global__ void __launch_bounds__(kGradThreads)
 #pragma unroll
     for (int q = 0; q < P; ++q) acc[q] = 0.0;
     const bool periodic = bc == 1;
-    const bool one_wrap = n2 >= g.reach[2];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tasks_per_row = (n2 + kGradTask - 1) / kGradTask;
@@ -87,82 +76,22 @@ __global__ void __launch_bounds__(kGradThreads)
         const int64_t row = tk / tasks_per_row;
         const int64_t c0 = (tk - row * tasks_per_row) * kGradTask;
         const int64_t x0 = row / n1, x1 = row - x0 * n1;
-        // rows at least `reach` inside the faces of axes 0 and 1 (uniform): the x
-        // neighbours of the row's end points wrap (periodic) or read 0 (zero halo)
-        // with one index correction and a select; one wrap is enough when the row
-        // is at least `reach` long
-        const bool inner = one_wrap && x0 >= g.reach[0] && x0 < n0 - g.reach[0] && x1 >= g.reach[1] &&
-                           x1 < n1 - g.reach[1];
-        if (BUF && inner) {
-            const uint32_t bytes = (uint32_t)(n0 * n1 * n2 * (int64_t)sizeof(S));
-            const rsrc_t rl = make_rsrc(lam, bytes), ru = make_rsrc(u, bytes);
-            const int m2 = (int)n2;
-            double l[kGradU];
-            int pc[kGradU], xc[kGradU];
 #pragma unroll
-            for (int i = 0; i < kGradU; ++i) {
-                const int x2 = (int)c0 + lane + 64 * i;
-                xc[i] = x2 < m2 ? x2 : m2 - 1;  // past the row's end: weight 0, address kept valid
-                pc[i] = (int)row * m2 + xc[i];
-                const double lv = load_f64<S>(rl, pc[i]);
-                l[i] = x2 < m2 ? lv : 0.0;
-            }
+        for (int i = 0; i < kGradU; ++i) {
+            const int64_t x2 = c0 + lane + 64 * i;
+            if (x2 >= n2) continue;
+            const double l = (double)to_compute(lam[row * n2 + x2]);
 #pragma unroll
             for (int q = 0; q < P; ++q) {
-                const int lin = (int)g.lin[q];
-#pragma unroll
-                for (int i = 0; i < kGradU; ++i) {
-                    const int y2 = xc[i] + g.ax[q][2];
-                    const int corr = y2 < 0 ? m2 : (y2 >= m2 ? -m2 : 0);
-                    const double v = load_f64<S>(ru, pc[i] + lin + corr);
-                    acc[q] = fma(l[i], (periodic || corr == 0) ? v : 0.0, acc[q]);
+                int64_t y0 = x0 + g.ax[q][0], y1 = x1 + g.ax[q][1], y2 = x2 + g.ax[q][2];
+                const bool inside = (y0 >= 0 && y0 < n0) && (y1 >= 0 && y1 < n1) && (y2 >= 0 && y2 < n2);
+                if (!inside) {
+                    y0 = wrap_index(y0, n0);
+                    y1 = wrap_index(y1, n1);
+                    y2 = wrap_index(y2, n2);
                 }
-            }
-        } else if (inner) {
-            double l[kGradU];
-            int64_t pc[kGradU];
-            int64_t xc[kGradU];
-#pragma unroll
-            for (int i = 0; i < kGradU; ++i) {
-                const int64_t x2 = c0 + lane + 64 * i;
-                xc[i] = x2 < n2 ? x2 : n2 - 1;  // past the row's end: weight 0, address kept valid
-                pc[i] = row * n2 + xc[i];
-                const double lv = (double)to_compute(lam[pc[i]]);
-                l[i] = x2 < n2 ? lv : 0.0;
-            }
-            // every slot runs (slots past nj hold offset 0 and are never folded), so
-            // the compiler can issue all P x kGradU loads before the first FMA waits
-#pragma unroll
-            for (int q = 0; q < P; ++q) {
-#pragma unroll
-                for (int i = 0; i < kGradU; ++i) {
-                    const int64_t y2 = xc[i] + g.ax[q][2];
-                    const int64_t corr = y2 < 0 ? n2 : (y2 >= n2 ? -n2 : 0);
-                    const double v = (double)to_compute(u[pc[i] + g.lin[q] + corr]);
-                    acc[q] = fma(l[i], (periodic || corr == 0) ? v : 0.0, acc[q]);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < kGradU; ++i) {
-                const int64_t x2 = c0 + lane + 64 * i;
-                if (x2 >= n2) continue;
-                const int64_t p = row * n2 + x2;
-                const double l = (double)to_compute(lam[p]);
-#pragma unroll
-                for (int q = 0; q < P; ++q) {
-                    {
-                        int64_t y0 = x0 + g.ax[q][0], y1 = x1 + g.ax[q][1], y2 = x2 + g.ax[q][2];
-                        const bool inside = (y0 >= 0 && y0 < n0) && (y1 >= 0 && y1 < n1) && (y2 >= 0 && y2 < n2);
-                        if (!inside) {
-                            y0 = wrap_index(y0, n0);
-                            y1 = wrap_index(y1, n1);
-                            y2 = wrap_index(y2, n2);
-                        }
-                        const double v = (double)to_compute(u[(y0 * n1 + y1) * n2 + y2]);
-                        acc[q] = fma(l, (inside || periodic) ? v : 0.0, acc[q]);
-                    }
-                }
+                const double v = (double)to_compute(u[(y0 * n1 + y1) * n2 + y2]);
+                acc[q] = fma(l, (inside || periodic) ? v : 0.0, acc[q]);
             }
         }
     }
@@ -457,7 +386,6 @@ static hipError_t launch_grad(const stencil_plan *p, const void *lam, const void
         GradOffsets g{};  // slots past nj: offset 0 (computed, never folded)
         for (int q = 0; q < nj; ++q) {
             const int *o = &off3[3 * (j0 + q)];
-            g.lin[q] = ((int64_t)o[0] * p->n1 + o[1]) * p->n2 + o[2];
             for (int i = 0; i < 3; ++i) {
                 g.ax[q][i] = o[i];
                 g.reach[i] = std::max(g.reach[i], std::abs(o[i]));
@@ -488,15 +416,11 @@ static hipError_t launch_grad(const stencil_plan *p, const void *lam, const void
                        : launch_tiled<S, 1, 2>(p, l, v, to, j0, nj, part, st);
             continue;
         }
-        const bool buf = p->points * (int64_t)sizeof(S) < ((int64_t)1 << 31);
         auto go = [&](auto kernel) {
             hipLaunchKernelGGL(kernel, dim3(kGradBlocks), dim3(kGradThreads), 0, st, l, v, p->n0, p->n1, p->n2, p->bc,
                                g, j0, nj, p->npts, part);
         };
-        if (nj <= 8)
-            buf ? go(coeff_grad_kernel<S, 8, true>) : go(coeff_grad_kernel<S, 8, false>);
-        else
-            buf ? go(coeff_grad_kernel<S, kGradMaxP, true>) : go(coeff_grad_kernel<S, kGradMaxP, false>);
+        nj <= 8 ? go(coeff_grad_kernel<S, 8>) : go(coeff_grad_kernel<S, kGradMaxP>);
     }
     return hipGetLastError();
 }
