@@ -53,12 +53,14 @@ def test_adjoint_matches_oracle(dim, r, kind, bc, dt):
 
 
 # ragged tiles along every axis (the coefficient-gradient kernels take tiles of
-# 8 x 8 x 64, 64 x 64 and 4096 points), axes shorter than a tile, and an axis
-# shorter than the stencil's reach (n0 = 1 with r = 2: the untiled kernel)
+# 8 x 8 x 64, 64 x 64 and 4096 points), axes shorter than a tile, an axis
+# shorter than the stencil's reach (n0 = 1 with r = 2: the untiled kernel), and
+# the 125-point box (four gradient passes of at most 32 offsets)
 @pytest.mark.parametrize("dim,r,kind,shape", [(3, 1, 1, (9, 17, 133)), (3, 2, 0, (13, 6, 70)),
                                               (3, 1, 0, (10, 10, 5)), (3, 2, 0, (1, 12, 40)),
                                               (2, 2, 1, (70, 150)), (2, 1, 0, (3, 200)),
-                                              (1, 2, 0, (9000,)), (1, 1, 0, (5,))])
+                                              (1, 2, 0, (9000,)), (1, 1, 0, (5,)),
+                                              (3, 2, 1, (7, 9, 70)), (2, 2, 0, (66, 65))])
 @pytest.mark.parametrize("bc", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_adjoint_ragged_tiles_match_oracle(dim, r, kind, shape, bc, dt):
