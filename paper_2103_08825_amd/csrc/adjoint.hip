@@ -12,6 +12,9 @@
 // across all steps (fixed order, no atomics); one fold at the end.
 #include <algorithm>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "device_common.hpp"
@@ -327,13 +330,38 @@ __global__ void __launch_bounds__(kGradThreads)
     fold_block<P>(acc, j0, nj, npts, part);
 }
 
+// Workgroups of a gradient launch: as many as the device holds at once (a
+// second, partial round would leave most compute units idle at its end), a
+// multiple of 8 (one share per XCD), at most the tiles and the partial slots.
+static int grad_grid(const void *kernel, int64_t ntile) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, int> resident;
+    int dev = 0, res = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = resident.find({dev, kernel});
+        if (it != resident.end()) {
+            res = it->second;
+        } else {
+            int per = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kGradThreads, 0) == hipSuccess &&
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+                res = per * cus;
+            resident[{dev, kernel}] = res;
+        }
+    }
+    int64_t grid = (ntile + 7) / 8 * 8;
+    if (res >= 8) grid = std::min<int64_t>(grid, res / 8 * 8);
+    return (int)std::min<int64_t>(grid, kGradBlocks);
+}
+
 template <typename S, int RH>
 static void launch_line(const stencil_plan *p, const S *lam, const S *u, const TileOffsets &g, int j0, int nj,
                         double *part, hipStream_t st) {
     const int64_t ntile = (p->n2 + kTileRows * 64 - 1) / (kTileRows * 64);
-    const int grid = (int)std::min<int64_t>(kGradBlocks, (ntile + 7) / 8 * 8);
     const bool buf = p->points * (int64_t)sizeof(S) < ((int64_t)1 << 31);
     auto go = [&](auto kernel) {
+        const int grid = grad_grid(reinterpret_cast<const void *>(kernel), ntile);
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(kGradThreads), 0, st, lam, u, p->n2, p->bc, g, j0, nj, p->npts,
                            part);
     };
@@ -345,11 +373,10 @@ static void launch_tiled(const stencil_plan *p, const S *lam, const S *u, const 
                          double *part, hipStream_t st) {
     using TS = TileShape<T1, RH>;
     const int64_t ntile = ((p->n0 + TS::T0 - 1) / TS::T0) * ((p->n1 + T1 - 1) / T1) * ((p->n2 + 63) / 64);
-    // a multiple of 8 (one share per XCD), at most the partial slots there are
-    const int grid = (int)std::min<int64_t>(kGradBlocks, (ntile + 7) / 8 * 8);
     // 32-bit indices when every element offset (and byte offset) fits
     const bool buf = p->points * (int64_t)sizeof(S) < ((int64_t)1 << 31);
     auto go = [&](auto kernel) {
+        const int grid = grad_grid(reinterpret_cast<const void *>(kernel), ntile);
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(kGradThreads), 0, st, lam, u, p->n0, p->n1, p->n2, p->bc, g, j0,
                            nj, p->npts, part);
     };
