@@ -171,6 +171,24 @@ static const Choice *measured_choice(const stencil_plan *p) {
     return nullptr;
 }
 
+// The measured one-step (k = 1) tiles were chosen on 512^3 grids.  One-step
+// launches wait on memory and want many waves in flight; when the measured tile
+// gives a 3D grid fewer than kPlainMinWaves waves, the smallest tile (1,4,8)
+// runs instead (measured at 256^3 FP32: 7-point 38 -> 29 us per step, 27-point
+// 70 -> 46 us, 13-point 53 -> 40 us; BF16 7-point 39 -> 32 us; at 384^3 7-point
+// 128 -> 115 us; at 512^3 the measured tiles stay ahead).
+constexpr int kPlainMinWaves = 16384;
+
+static void plain_choice(const stencil_plan *p, const Choice *mc, int *variant, int *chunk) {
+    *variant = mc->pvariant;
+    *chunk = mc->pchunk;
+    VariantShape v, v1;
+    if (p->dim != 3 || mc->pvariant == 1 || !shape_of(3, mc->pvariant, &v) || !shape_of(3, 1, &v1)) return;
+    if (!variant_fits_shape(p, 1) || max_k_of(p, 1) < 1) return;
+    const Geometry g = stream_geometry(3, p->r, 1, v, p->n0, p->n1, p->n2, mc->pchunk);
+    if (g.ok && (int64_t)g.nblocks * (g.threads / 64) < kPlainMinWaves) *variant = 1;
+}
+
 // Resolve the requested method into an execution choice.  Returns a status.
 static int resolve_exec(stencil_plan *p) {
     const stencil_opts &o = p->opts;
@@ -200,11 +218,12 @@ static int resolve_exec(stencil_plan *p) {
     const Choice *mc = measured_choice(p);
     int chunk = o.chunk;
     if (mc && o.variant == 0) {
-        const int mv = method == STENCIL_METHOD_PLAIN ? mc->pvariant : mc->variant;
+        int mv = mc->variant, mchunk = mc->chunk;
+        if (method == STENCIL_METHOD_PLAIN) plain_choice(p, mc, &mv, &mchunk);
         const int need_k = method == STENCIL_METHOD_FUSED && o.fused_k > 0 ? o.fused_k : 1;
         if (variant_fits_shape(p, mv) && max_k_of(p, mv) >= need_k) {
             variant = mv;
-            if (o.chunk == 0) chunk = method == STENCIL_METHOD_PLAIN ? mc->pchunk : mc->chunk;
+            if (o.chunk == 0) chunk = mchunk;
         }
     }
     if (variant == 0 || max_k_of(p, variant) < 1) {
@@ -368,9 +387,13 @@ Exec one_step_exec(const stencil_plan *p) {
     ex.k = 1;
     ex.chunk = 0;
     const Choice *mc = measured_choice(p);
-    if (mc && variant_fits_shape(p, mc->pvariant) && max_k_of(p, mc->pvariant) >= 1) {
-        ex.variant = mc->pvariant;
-        ex.chunk = mc->pchunk;
+    if (mc) {
+        int pv = 0, pc = 0;
+        plain_choice(p, mc, &pv, &pc);
+        if (variant_fits_shape(p, pv) && max_k_of(p, pv) >= 1) {
+            ex.variant = pv;
+            ex.chunk = pc;
+        }
     }
     return ex;
 }
