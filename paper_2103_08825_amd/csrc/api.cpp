@@ -171,22 +171,22 @@ static const Choice *measured_choice(const stencil_plan *p) {
     return nullptr;
 }
 
-// The measured one-step (k = 1) tiles were chosen on 512^3 grids.  One-step
-// launches wait on memory and want many waves in flight; when the measured tile
-// gives a 3D grid fewer than kPlainMinWaves waves, the smallest tile (1,4,8)
-// runs instead (measured at 256^3 FP32: 7-point 38 -> 29 us per step, 27-point
-// 70 -> 46 us, 13-point 53 -> 40 us; BF16 7-point 39 -> 32 us; at 384^3 7-point
-// 128 -> 115 us; at 512^3 the measured tiles stay ahead).
-constexpr int kPlainMinWaves = 16384;
+// The measured one-step (k = 1) choices were made on 512^3 grids.  One-step
+// launches wait on memory and want many waves in flight, so a 3D grid of fewer
+// than kPlainSmallGrid points (half of 512^3) takes the smallest tile (1,4,8)
+// with chunks of at most 8 planes instead (measured at 256^3 FP32: 7-point
+// 38 -> 29 us per step, 27-point 70 -> 46 us, 13-point 53 -> 40 us; BF16 7-point
+// 39 -> 32 us; at 384^3 FP32 7-point 128 -> 115 us; at 128^3 FP64 7-point, chunks
+// of 32 -> 8 planes: 77 -> 118 GStencil/s).
+constexpr int64_t kPlainSmallGrid = (int64_t)1 << 26;
 
 static void plain_choice(const stencil_plan *p, const Choice *mc, int *variant, int *chunk) {
     *variant = mc->pvariant;
     *chunk = mc->pchunk;
-    VariantShape v, v1;
-    if (p->dim != 3 || mc->pvariant == 1 || !shape_of(3, mc->pvariant, &v) || !shape_of(3, 1, &v1)) return;
+    if (p->dim != 3 || p->points >= kPlainSmallGrid) return;
     if (!variant_fits_shape(p, 1) || max_k_of(p, 1) < 1) return;
-    const Geometry g = stream_geometry(3, p->r, 1, v, p->n0, p->n1, p->n2, mc->pchunk);
-    if (g.ok && (int64_t)g.nblocks * (g.threads / 64) < kPlainMinWaves) *variant = 1;
+    *variant = 1;
+    if (*chunk > 8) *chunk = 8;
 }
 
 // Resolve the requested method into an execution choice.  Returns a status.
