@@ -181,3 +181,24 @@ def test_requested_depth_picks_a_variant_compiled_that_deep(L):
     _lib.stencil_plan_destroy(h)
     rc, h = _create(L, (64, 64, 64), 1, 1, [1 / 27] * 27, 0, _lib.F32, method=_lib.METHOD_FUSED, fused_k=99)
     assert rc == _lib.STENCIL_E_UNSUPPORTED and "exceeds" in _lib.last_error()
+
+
+def test_one_step_tile_follows_the_grid_size(L):
+    # one-step sweeps keep the measured 512^3 tile on large grids and take the
+    # smallest 3D tile, with chunks of at most 8 planes, below half of 512^3
+    c7 = [0.1] * 7
+    rc, h = _create(L, (512, 512, 512), 1, 0, c7, 0, _lib.F32, method=_lib.METHOD_PLAIN)
+    assert rc == 0, _lib.last_error()
+    big = _lib.stencil_plan_info(h)
+    _lib.stencil_plan_destroy(h)
+    rc, h = _create(L, (256, 256, 256), 1, 0, c7, 0, _lib.F32, method=_lib.METHOD_PLAIN)
+    assert rc == 0, _lib.last_error()
+    small = _lib.stencil_plan_info(h)
+    _lib.stencil_plan_destroy(h)
+    assert big["variant"] != 1 and small["variant"] == 1
+    assert small["tile"][2] <= 8
+    rc, h = _create(L, (128, 128, 128), 1, 0, c7, 0, _lib.F64, method=_lib.METHOD_PLAIN)
+    assert rc == 0, _lib.last_error()
+    f64 = _lib.stencil_plan_info(h)
+    _lib.stencil_plan_destroy(h)
+    assert f64["variant"] == 1 and f64["tile"][2] <= 8
