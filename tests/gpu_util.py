@@ -38,3 +38,22 @@ def gpu_sweep(plan, t_in: torch.Tensor, T: int) -> np.ndarray:
     out = plan.run(d_in, T)
     torch.cuda.synchronize()
     return out.to(torch.float64).cpu().numpy()
+
+
+def record_error(key: str, rec: dict) -> None:
+    """Adds one result's error record to the JSON file named by the environment
+    variable STENCIL_ERROR_TABLE (no-op when it is unset)."""
+    import json
+    import os
+    path = os.environ.get("STENCIL_ERROR_TABLE")
+    if not path:
+        return
+    table = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+    table[key] = rec
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)

@@ -279,3 +279,69 @@ def test_graph_replays_match_eager_runs(method):
         g3.run(x3, c3.T, out=y3)
         torch.cuda.synchronize()
         assert torch.equal(y3, e3.run(x3, c3.T)), rep
+
+
+# tile shapes (columns per lane, waves, rows per wave) of the 3D variant ids
+V3 = {1: (1, 4, 8), 2: (1, 8, 8), 3: (2, 4, 8), 4: (1, 8, 4), 5: (1, 16, 4), 6: (2, 8, 4)}
+INTERIOR_SHAPE = (40, 140, 256)
+
+
+def _unmasked_workgroups(shape, r, k, variant, tile):
+    """Workgroups of a zero-halo 3D launch whose widened tile and every plane
+    their outputs depend on lie inside the grid: the ones that take the
+    kernel's path without per-point boundary masks."""
+    n0, n1, n2 = shape
+    vx, nw, rw = V3[variant]
+    out_x, out_y, chunk = tile
+    halo_x = -(-k * r // vx) * vx
+    count = 0
+    for zc in range(-(-n0 // chunk)):
+        z0, z1 = zc * chunk, min(zc * chunk + chunk, n0)
+        if z0 - k * r < 0 or z1 + k * r > n0:
+            continue
+        for ty in range(-(-n1 // out_y)):
+            yb = ty * out_y - k * r
+            if yb < 0 or yb + nw * rw > n1:
+                continue
+            for tx in range(-(-n2 // out_x)):
+                xb = tx * out_x - halo_x
+                if 0 <= xb and xb + 64 * vx <= n2:
+                    count += 1
+    return count
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("name", ["3d7p", "3d27p", "3d13p"])
+def test_default_tiles_on_interior_reaching_grid(name, dt):
+    """The 512^3 defaults (tile variant and fused depth of every stencil and
+    storage type, and the plain comparator's tile) on a grid with tiles that lie
+    wholly inside it, so that the unmasked zero-halo path runs next to the
+    masked one; element-wise against the oracle, with a remainder pass."""
+    big = W.case_3d(name, seed=0, n=8, T=1)   # only its stencil and weights
+    ref_plan = Plan((512, 512, 512), big.r, big.kind, big.coeffs, W.BC_ZERO, dt)
+    info512 = ref_plan.info()
+    ref_plan.close()
+    rng = np.random.default_rng(17)
+    u0 = rng.uniform(-1, 1, INTERIOR_SHAPE)
+    t_in, u_ex, c_ex = rounded_inputs(u0, big.coeffs, dt)
+    runs = [("fused", info512["variant"], info512["fused_k"])]
+    if dt == "f32":
+        pl = Plan((512, 512, 512), big.r, big.kind, big.coeffs, W.BC_ZERO, dt, method="plain")
+        runs.append(("plain", pl.info()["variant"], 1))
+        pl.close()
+    for method, variant, k in runs:
+        plan = Plan(INTERIOR_SHAPE, big.r, big.kind, big.coeffs, W.BC_ZERO, dt, method=method,
+                    fused_k=k if method == "fused" else 0, variant=variant, chunk=8)
+        info = plan.info()
+        assert (info["variant"], info["fused_k"]) == (variant, k)
+        inner = _unmasked_workgroups(INTERIOR_SHAPE, big.r, k, variant, info["tile"])
+        assert inner > 0, info
+        T = 2 * k + 1
+        say("interior %s %s %s variant=%d k=%d tile=%s T=%d (%d unmasked workgroups)"
+            % (name, dt, method, variant, k, info["tile"], T, inner))
+        got = gpu_sweep(plan, t_in, T)
+        ref = oracle.run(u_ex, c_ex, T, r=big.r, kind=big.kind, bc=W.BC_ZERO)
+        err = rel_err(got, ref)
+        say("  rel err %.3e" % err)
+        assert err <= TOL[dt]
+        plan.close()
