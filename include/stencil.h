@@ -208,6 +208,18 @@ int stencil_adjoint(stencil_plan *p, const void *d_u0, const void *d_gT, int64_t
 int stencil_reduce(int dtype, const void *d_u, const void *d_ref, int64_t n, double *d_out,
                    void *stream);
 
+/* The same reduction without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, result and determinism are those of
+ * stencil_reduce (the same kernels; bitwise the same result).  The partial
+ * rows live in a fixed 96 KiB device array (2048 rows of 6 doubles), one per
+ * GPU, held until the process ends; a reduction never needs more rows,
+ * whatever n, so no n is rejected for size.  Every call on a GPU shares that
+ * array: calls that overlap on one GPU (two streams, or two threads) race and
+ * must be serialised by the caller. */
+int stencil_reduce_noalloc(int dtype, const void *d_u, const void *d_ref, int64_t n, double *d_out,
+                           void *stream);
+
 /* --- errors ------------------------------------------------------------------ */
 
 /* Message of the calling thread's last failure ("" if none).  The pointer

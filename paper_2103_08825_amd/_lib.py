@@ -30,7 +30,7 @@ EXPORTS = (
     "stencil_num_points", "stencil_offsets", "stencil_plan_create", "stencil_plan_destroy",
     "stencil_plan_info", "stencil_plan_prepare", "stencil_autotune", "stencil_run",
     "stencil_run_batched", "stencil_batch_create", "stencil_batch_launch", "stencil_batch_destroy",
-    "stencil_batch_info", "stencil_batch_status", "stencil_adjoint", "stencil_reduce", "stencil_last_error",
+    "stencil_batch_info", "stencil_batch_status", "stencil_adjoint", "stencil_reduce", "stencil_reduce_noalloc", "stencil_last_error",
     "stencil_version",
 )
 
@@ -88,6 +88,7 @@ def lib():
             "stencil_batch_status": (ci, [vp, vp]),
             "stencil_adjoint": (ci, [vp, vp, vp, i64, i64, vp, vp, vp]),
             "stencil_reduce": (ci, [ci, vp, vp, i64, vp, vp]),
+            "stencil_reduce_noalloc": (ci, [ci, vp, vp, i64, vp, vp]),
             "stencil_last_error": (ctypes.c_char_p, []),
             "stencil_version": (ci, []),
         }
@@ -210,6 +211,11 @@ def stencil_adjoint(plan: int, d_u0: int, d_gT: int, T: int, ckpt: int, d_grad_u
 
 def stencil_reduce(dtype: int, d_u: int, d_ref: int, n: int, d_out: int, stream: int) -> None:
     check(lib().stencil_reduce(dtype, d_u, d_ref or None, int(n), d_out, stream), "stencil_reduce")
+
+
+def stencil_reduce_noalloc(dtype: int, d_u: int, d_ref: int, n: int, d_out: int, stream: int) -> None:
+    check(lib().stencil_reduce_noalloc(dtype, d_u, d_ref or None, int(n), d_out, stream),
+          "stencil_reduce_noalloc")
 
 
 def stencil_version() -> int:

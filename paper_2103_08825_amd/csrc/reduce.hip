@@ -2,8 +2,11 @@
 // max |u|, and the same against a reference field.  Fixed partial layout
 // (kReduceBlocks x 256 threads, grid-stride order, fixed tree order), so the
 // result is deterministic for a given element count.
+#include <mutex>
+
 #include "device_common.hpp"
 #include "launch.hpp"
+#include "plan.hpp"
 
 namespace stn {
 
@@ -163,3 +166,59 @@ hipError_t launch_reduce(int dtype, const void *u, const void *ref, int64_t n, d
 }
 
 }  // namespace stn
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of the reduction: the partial rows live in a fixed
+// device array instead of a stream-ordered allocation.  A launch never uses
+// more than kReduceBlocks rows, whatever n is, so the array has a fixed size.
+namespace stn {
+
+constexpr int kScratchDoubles = kReduceBlocks * 6;  // 96 KiB
+constexpr int kMaxDevices = 64;
+
+// In host code this name is only a stand-in for the symbol: the device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+
+// The current device's copy of `scratch` (looked up on the first call on each
+// device, with that device current).
+static int scratch_for_current_device(double **out) {
+    int dev = 0;
+    STN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(STENCIL_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(STENCIL_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return STENCIL_OK;
+}
+
+}  // namespace stn
+
+extern "C" int stencil_reduce_noalloc(int dtype, const void *d_u, const void *d_ref, int64_t n,
+                                      double *d_out, void *stream) {
+    using namespace stn;
+    clear_error();
+    if (elem_bytes(dtype) == 0) return fail(STENCIL_E_INVALID, "unknown dtype %d", dtype);
+    if (n < 0) return fail(STENCIL_E_INVALID, "n must be >= 0");
+    if (!d_out || (!d_u && n > 0)) return fail(STENCIL_E_INVALID, "NULL pointer");
+    if (reduce_partials_bytes() > (int)sizeof(scratch))
+        return fail(STENCIL_E_INVALID, "partial rows need %d bytes, the fixed scratch holds %d",
+                    reduce_partials_bytes(), (int)sizeof(scratch));
+    double *part = nullptr;
+    const int rc = scratch_for_current_device(&part);
+    if (rc != STENCIL_OK) return rc;
+    // every partial row the final fold reads is written by this call's first
+    // kernel, so nothing needs clearing
+    const hipError_t e = launch_reduce(dtype, d_u, d_ref, n, part, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(STENCIL_E_DEVICE, "reduction launch: %s", hipGetErrorString(e));
+    return STENCIL_OK;
+}
