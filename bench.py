@@ -70,19 +70,42 @@ def time_sweep(plan, x, y, T, steps, warmup, with_reduce=True):
     return total, sweep, wall
 
 
-def cpu_baseline(u0_f64, coeffs, r, kind, bc, budget_s=12.0):
-    """The oracle as it stands, on the host cores, over a bounded number of steps
-    of the same grid."""
+def cpu_model() -> str:
+    """The host CPU's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(u0_f64, coeffs, r, kind, bc, T, budget_s=12.0, budget_1t_s=6.0):
+    """The oracle as it stands on the host cores (all of them, then one thread),
+    each over a bounded number of steps of the same grid."""
     import oracle
     threads = oracle.max_threads()
     _, s1 = oracle.run(u0_f64, coeffs, 1, r=r, kind=kind, bc=bc, return_seconds=True)
-    steps = max(1, min(64, int(budget_s / max(s1, 1e-3))))
+    steps = max(1, min(T, int(budget_s / max(s1, 1e-3))))
     _, secs = oracle.run(u0_f64, coeffs, steps, r=r, kind=kind, bc=bc, return_seconds=True)
     pts = u0_f64.size * steps
+    grid = "x".join(str(s) for s in u0_f64.shape)
+    # one thread: a shorter run of the same grid, scaled per point-step
+    _, s1t = oracle.run(u0_f64, coeffs, 1, r=r, kind=kind, bc=bc, nthreads=1, return_seconds=True)
+    steps1 = max(1, min(T, int(budget_1t_s / max(s1t, 1e-3))))
+    if steps1 > 1:
+        _, s1t = oracle.run(u0_f64, coeffs, steps1, r=r, kind=kind, bc=bc, nthreads=1, return_seconds=True)
     return {"value": pts / secs / 1e9, "unit": "GStencil/s", "cores": threads, "kind": "oracle",
-            "sample": "full %s grid, %d of the 64 steps (FP64 loop nest, OpenMP over the grid)"
-                      % ("x".join(str(s) for s in u0_f64.shape), steps),
-            "seconds": secs}
+            "cpu_model": cpu_model(),
+            "sample": "full %s grid, %d of the %d steps (FP64 loop nest, OpenMP over the grid)"
+                      % (grid, steps, T),
+            "seconds": secs,
+            "single_thread": {"value": u0_f64.size * steps1 / s1t / 1e9, "unit": "GStencil/s",
+                              "cores": 1, "seconds": s1t,
+                              "sample": "full %s grid, %d of the %d steps on one thread "
+                                        "(a shorter T, rate per point-step)" % (grid, steps1, T)}}
 
 
 def copy_bandwidth(x, y, reps=10):
@@ -362,6 +385,7 @@ def main(argv=None):
     ap.add_argument("--T", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 sub-record")
     ap.add_argument("--autotune", action="store_true",
                     help="time every compiled (variant, k, chunk) first instead of the "
                          "library's measured default")
@@ -481,13 +505,29 @@ def main(argv=None):
                 "note": "useful FMAs only; the recomputed tile halo and the chunk fill add "
                         "issued VALU work (see profiles/stream3d_7p_512_f32_sq_counters.md)"}
 
+    # the paper's own precision (FP64) on the same grid and steps, library defaults
+    f64_rec = None
+    if not a.no_f64:
+        x64 = torch.from_numpy(case.u0).cuda()
+        y64 = torch.empty_like(x64)
+        p64 = Plan(case.shape, case.r, case.kind, case.coeffs, case.bc, "f64")
+        ms64, sw64, _ = time_sweep(p64, x64, y64, T, max(2, a.steps // 2), 1, with_reduce=False)
+        i64 = p64.info()
+        f64_rec = {"value": points * T / (ms64 * 1e-3) / 1e9, "unit": "GStencil/s", "ms_per_step": ms64,
+                   "fused_k": i64["fused_k"], "variant": i64["variant"], "tile": i64["tile"],
+                   "hbm_frac_alg": 2.0 * 8 * points * (-(-T // i64["fused_k"])) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log("fp64: %.3f ms/step, %.1f GStencil/s (k=%d)" % (ms64, f64_rec["value"], i64["fused_k"]))
+        p64.close()
+        del x64, y64
+
     cpu = None
     if not a.no_cpu_baseline:
         log("cpu baseline ...")
         c32 = case.coeffs.astype(np.float32).astype(np.float64)
         u32 = x.double().cpu().numpy()
-        cpu = cpu_baseline(u32, c32, case.r, case.kind, case.bc)
-        log("cpu: %.3f GStencil/s on %d threads" % (cpu["value"], cpu["cores"]))
+        cpu = cpu_baseline(u32, c32, case.r, case.kind, case.bc, T)
+        log("cpu: %.3f GStencil/s on %d threads, %.3f on one (%s)"
+            % (cpu["value"], cpu["cores"], cpu["single_thread"]["value"], cpu["cpu_model"]))
 
     rec = {
         "metric": METRIC, "value": gst, "unit": "GStencil/s", "n_gpus": 1, "steps": a.steps,
@@ -500,6 +540,7 @@ def main(argv=None):
         "plain": plain_rec,
         "speedup_vs_plain": (plain_rec["ms_per_step"] / ms) if plain_rec else None,
         "roofline": roof, "roofline_alu": roof_alu, "cpu_baseline": cpu,
+        "fp64": f64_rec,
     }
     print(json.dumps(rec), flush=True)
     fused.close()

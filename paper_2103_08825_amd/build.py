@@ -41,15 +41,36 @@ def _headers():
             glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
+def _deps_newest(dep: str) -> float | None:
+    """Newest modification time of the files a make-style dependency file lists
+    (None if it is missing or names a file that no longer exists)."""
+    try:
+        with open(dep) as f:
+            text = f.read().replace("\\\n", " ")
+    except OSError:
+        return None
+    _, _, rest = text.partition(":")
+    newest = 0.0
+    for name in rest.split():
+        try:
+            newest = max(newest, os.path.getmtime(name))
+        except OSError:
+            return None
+    return newest
+
+
 def _compile(src: str, incremental: bool, newest_header: float) -> tuple[str, float, str]:
     obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
+    dep = obj + ".d"
     if incremental and os.path.exists(obj):
         t = os.path.getmtime(obj)
-        if t >= os.path.getmtime(src) and t >= newest_header:
+        deps = _deps_newest(dep)
+        newest = deps if deps is not None else max(os.path.getmtime(src), newest_header)
+        if t >= newest:
             return obj, 0.0, ""
     t0 = time.time()
     tmp = obj + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", tmp]
+    cmd = [HIPCC] + FLAGS + ["-MMD", "-MF", dep, "-c", src, "-o", tmp]
     p = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (p.stdout + p.stderr).splitlines() if "packed-fp32-ops" not in l)
     if p.returncode != 0:

@@ -490,16 +490,19 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
         }
     // workspace (stream ordered): checkpoints 1..nseg-1, segment states 1..seglen-1,
     // two adjoint fields, partial sums, offset tables
+    // every sub-buffer starts on a 256-byte boundary (the lane width chosen from
+    // the caller's pointers assumes workspace fields at least as aligned)
     const int64_t nck = nseg - 1, nst = seglen - 1;
+    const size_t fstride = (field + 255) & ~(size_t)255;
     const size_t part_bytes = (size_t)kGradBlocks * p->npts * sizeof(double);
     const size_t tab_bytes = off3m.size() * sizeof(int);
-    const size_t ws_bytes = (size_t)(nck + nst + 2) * field + part_bytes + tab_bytes + 256;
+    const size_t ws_bytes = (size_t)(nck + nst + 2) * fstride + part_bytes + tab_bytes;
     char *ws = nullptr;
     STN_HIP(hipMallocAsync((void **)&ws, ws_bytes, st));
-    auto ck = [&](int64_t s) -> void * { return s == 0 ? const_cast<void *>(d_u0) : ws + (size_t)(s - 1) * field; };
-    char *seg_base = ws + (size_t)nck * field;
-    char *lam_buf[2] = {ws + (size_t)(nck + nst) * field, ws + (size_t)(nck + nst + 1) * field};
-    double *part = reinterpret_cast<double *>(ws + (size_t)(nck + nst + 2) * field);
+    auto ck = [&](int64_t s) -> void * { return s == 0 ? const_cast<void *>(d_u0) : ws + (size_t)(s - 1) * fstride; };
+    char *seg_base = ws + (size_t)nck * fstride;
+    char *lam_buf[2] = {ws + (size_t)(nck + nst) * fstride, ws + (size_t)(nck + nst + 1) * fstride};
+    double *part = reinterpret_cast<double *>(ws + (size_t)(nck + nst + 2) * fstride);
     int *d_offm = reinterpret_cast<int *>(reinterpret_cast<char *>(part) + part_bytes);
     int rc = STENCIL_OK;
     auto done = [&](int code) {
@@ -519,7 +522,7 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
     for (int64_t s = nseg - 1; s >= 0; --s) {
         const int64_t tb = s * C, te = (tb + C < T) ? tb + C : T;
         auto state = [&](int64_t t) -> const void * {
-            return t == tb ? ck(s) : static_cast<const void *>(seg_base + (size_t)(t - tb - 1) * field);
+            return t == tb ? ck(s) : static_cast<const void *>(seg_base + (size_t)(t - tb - 1) * fstride);
         };
         for (int64_t t = tb + 1; t < te && rc == STENCIL_OK; ++t)
             rc = one_step(p, ex1, p->dense, p->d_off, p->d_coef, state(t - 1), const_cast<void *>(state(t)), st);
