@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OBJ_DIR = os.path.join(ROOT, "_build", "obj")
+GEN_DIR = os.path.join(ROOT, "_build", "gen")  # generated kernel-instance units
 LIB = os.path.join(HERE, "libstencil.so")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -27,13 +28,19 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=%s" % ARCH,
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I%s" % os.path.join(ROOT, "include"),
+    "-I%s" % os.path.join(ROOT, "include"), "-I%s" % CSRC,
     "-Wall", "-Wno-unused-command-line-argument",
 ]
 
 
 def _sources():
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    sys.path.insert(0, CSRC)
+    try:
+        import gen_instances
+    finally:
+        sys.path.pop(0)
+    generated = gen_instances.write_units(GEN_DIR)
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")) + generated)
 
 
 def _headers():
