@@ -68,8 +68,17 @@ enum stencil_method {
     STENCIL_METHOD_AUTO = 0,    /* fused when a fused kernel fits the plan, else plain */
     STENCIL_METHOD_PLAIN = 1,   /* one time step per launch (the fused kernel with k = 1) */
     STENCIL_METHOD_FUSED = 2,   /* k time steps per launch */
-    STENCIL_METHOD_GENERIC = 3  /* reference kernel: any d, r <= 4, one step per launch,
+    STENCIL_METHOD_GENERIC = 3, /* reference kernel: any d, r <= 4, one step per launch,
                                    every neighbour read straight from memory */
+    STENCIL_METHOD_TESSELLATE = 4 /* 3D only: k steps per pass without recomputing a y
+                                   halo, as the two stages of the tessellated tiling of
+                                   Section 3.4 (trapezoids along y, then the inverted
+                                   trapezoids around the cuts, in two launches; the
+                                   intermediate rows the second stage needs go through
+                                   a plan-owned slope buffer).  Same results as
+                                   STENCIL_METHOD_FUSED, bit for bit.  Needs a y extent
+                                   of at least 2(k+1)r; STENCIL_E_UNSUPPORTED when no
+                                   tessellated kernel is compiled for the stencil. */
 };
 
 typedef struct stencil_plan stencil_plan;   /* opaque, library-owned */
@@ -91,6 +100,17 @@ typedef struct stencil_opts {
                      triple into a HIP graph on its first call and replays the graph
                      while later calls repeat the triple (a new triple, autotuning or
                      a device change re-records); for launch-bound small grids */
+    int inplace;  /* nonzero: fused passes update one field in place instead of
+                     ping-ponging with a second one (Section 3.3, last paragraph:
+                     with every pass ending at the same time level, the input's
+                     space can hold the output).  The points a pass's other
+                     workgroups still read (the bands of every output tile) go
+                     through a plan-owned side buffer and are copied in by a
+                     second kernel per pass; the plan holds no ping-pong field,
+                     and d_in == d_out needs no copy of the input.  Results are
+                     bitwise those of the ping-pong plan.  Fused and plain methods
+                     only; STENCIL_E_UNSUPPORTED when no in-place kernel is
+                     compiled for the plan's stencil, variant and depth. */
 } stencil_opts;
 
 /* What a plan resolved to (stencil_plan_info). */
@@ -115,10 +135,14 @@ typedef struct stencil_plan_desc {
 int stencil_num_points(int dim, int radius, int kind);
 
 /* Writes the offset set in canonical order to out[npts*dim] (host memory,
- * offset j at out[j*dim .. j*dim+dim-1]).  Returns npts or a negative code. */
+ * offset j at out[j*dim .. j*dim+dim-1]).  Returns npts or a negative code.
+ * The offset sets are those of Section 1 (star and box of order r); the paper
+ * fixes no order for the weights, so the canonical order is this library's. */
 int stencil_offsets(int dim, int radius, int kind, int32_t *out);
 
-/* Creates a plan.  shape: dim extents (host, slowest first, each >= 1).
+/* Creates a plan for the operation of Section 1 (one constant weight per
+ * offset) on one grid; the fused depth k is the time-loop unroll of
+ * Section 3.3.  shape: dim extents (host, slowest first, each >= 1).
  * coeffs: ncoeffs = stencil_num_points(dim, radius, kind) doubles in
  * canonical order (host; copied).  r must be 1..STENCIL_MAX_RADIUS.
  * Allocates no device memory.  On failure *out is set to NULL. */
@@ -127,24 +151,34 @@ int stencil_plan_create(stencil_plan **out, int dim, const int64_t *shape, int r
                         const stencil_opts *opts);
 
 /* Frees the plan and its device memory (NULL-safe).  Waits for nothing: the
- * caller must have synchronised any stream still using the plan. */
+ * caller must have synchronised any stream still using the plan.  (Library
+ * housekeeping; no passage of the paper.) */
 void stencil_plan_destroy(stencil_plan *p);
 
-/* Fills *out with the plan's resolved configuration. */
+/* Fills *out with the plan's resolved configuration (library housekeeping). */
 int stencil_plan_info(const stencil_plan *p, stencil_plan_desc *out);
 
 /* Allocates the plan's device scratch on the current device now (otherwise
- * done by the first run).  Needed before capturing stencil_run in a graph. */
+ * done by the first run).  Needed before capturing stencil_run in a graph.
+ * (Library housekeeping.) */
 int stencil_plan_prepare(stencil_plan *p, void *stream);
 
-/* Times every candidate (variant, k) of the plan on its own scratch buffers,
- * on `stream`, and keeps the fastest.  Synchronises the stream.  The result
- * is also cached per process under the plan's signature. */
+/* Times every candidate (variant, k, chunk) of the plan on its own scratch
+ * buffers, on `stream`, and keeps the fastest.  Synchronises the stream.
+ * The paper tunes its block sizes and k by hand (Section 4.1) and leaves
+ * tuning to future work; this is the library's extension.  The result is
+ * cached under a signature of the device architecture, the stencil, the
+ * grid and the options that narrow the candidates, in memory and in the file
+ * named by STENCIL_TUNE_CACHE (unset: $XDG_CACHE_HOME or ~/.cache,
+ * paper_2103_08825_amd/autotune.txt; empty: memory only); entries a plan
+ * cannot run, and unreadable or corrupt files, are ignored.  Plans created
+ * with the tessellated method or in place keep their measured choice. */
 int stencil_autotune(stencil_plan *p, void *stream);
 
 /* --- sweeps ------------------------------------------------------------------- */
 
-/* u_T = T steps of the plan's stencil applied to u_0.
+/* u_T = T steps of the plan's stencil applied to u_0 (Section 1), k steps
+ * per pass over the data (Section 3.3, Algorithm 1: the multistep update).
  * d_in: u_0 (read only); d_out: u_T; both prod(shape) elements of the plan's
  * dtype in device memory.  d_in == d_out is allowed (the input is copied to
  * scratch first).  T == 0 copies d_in to d_out.  The T steps run as
@@ -153,14 +187,16 @@ int stencil_run(stencil_plan *p, const void *d_in, void *d_out, int64_t T, void 
 
 /* n independent sweeps, each with its own plan (2D plans, any r <= 2, star or
  * box, any bc, same dtype across the batch), input, output and step count,
- * executed by one persistent kernel launch.  d_in[i] and d_out[i] must not
+ * executed by one persistent kernel launch.  Not in the paper: the library's
+ * extension for many small, uneven grids.  d_in[i] and d_out[i] must not
  * alias any buffer of another batch member, and d_in[i] != d_out[i].
  * Equivalent to stencil_batch_create + stencil_batch_launch + destroy. */
 int stencil_run_batched(stencil_plan *const *plans, int n, const void *const *d_in,
                         void *const *d_out, const int64_t *T, void *stream);
 
 /* Builds the work list of a batch once (host), uploads it, and captures the
- * counter reset and the persistent kernel into a HIP graph.  The plans and
+ * counter reset and the persistent kernel into a HIP graph (the batched
+ * extension, not in the paper).  The plans and
  * buffers must outlive the batch.  Each replay recomputes the outputs from the
  * inputs.  Per grid, a pass runs the plan's requested fused depth (opts.fused_k),
  * one step for plans created with the plain or generic method, else the deepest
@@ -171,20 +207,23 @@ int stencil_run_batched(stencil_plan *const *plans, int n, const void *const *d_
 int stencil_batch_create(stencil_batch **out, stencil_plan *const *plans, int n,
                          const void *const *d_in, void *const *d_out, const int64_t *T,
                          int flags, void *stream);
-/* Replays the captured graph on `stream`. */
+/* Replays the captured graph on `stream` (batched extension). */
 int stencil_batch_launch(stencil_batch *b, void *stream);
-/* Frees the batch (NULL-safe); the caller must have synchronised its stream. */
+/* Frees the batch (NULL-safe); the caller must have synchronised its stream
+ * (batched extension). */
 void stencil_batch_destroy(stencil_batch *b);
-/* Number of work items and of persistent workgroups of a batch. */
+/* Number of work items and of persistent workgroups of a batch (batched
+ * extension). */
 int stencil_batch_info(const stencil_batch *b, int64_t *items, int64_t *workgroups);
 /* Synchronises `stream` and reports whether the last replay completed every
- * work item: STENCIL_E_DEVICE if a work item gave up waiting for its
+ * work item (batched extension): STENCIL_E_DEVICE if a work item gave up waiting for its
  * predecessor (a bounded wait; it cannot happen with a well-formed list). */
 int stencil_batch_status(const stencil_batch *b, void *stream);
 
 /* --- derivative --------------------------------------------------------------- */
 
-/* Reverse-mode derivative of u_T = stencil_run(u_0, T).  Given
+/* Reverse-mode derivative of u_T = stencil_run(u_0, T).  Not in the paper:
+ * the library's extension for gradients through the sweep of Section 1.  Given
  * d_gT = dL/du_T (device, plan dtype), writes d_grad_u0 = dL/du_0 (device,
  * plan dtype) and d_grad_coeffs[j] = dL/dc_j (device, ncoeffs doubles,
  * overwritten).  The adjoint step is the mirrored stencil (weight c_j at
@@ -200,7 +239,8 @@ int stencil_adjoint(stencil_plan *p, const void *d_u0, const void *d_gT, int64_t
 /* --- FP64 reductions ---------------------------------------------------------- */
 
 /* Reduces n elements of dtype at d_u (and d_ref if not NULL, same dtype) in
- * FP64 into d_out[6] (device doubles):
+ * FP64 into d_out[6] (device doubles) -- checksums and norms of results, a
+ * library extension (the paper has no reduction):
  *   [0] sum u   [1] sum u^2   [2] max |u|
  *   [3] sum (u-ref)^2   [4] max |u-ref|   [5] max |ref|   (0 when d_ref is NULL)
  * The result is deterministic for a given n and pointer alignment (fixed
@@ -223,10 +263,10 @@ int stencil_reduce_noalloc(int dtype, const void *d_u, const void *d_ref, int64_
 /* --- errors ------------------------------------------------------------------ */
 
 /* Message of the calling thread's last failure ("" if none).  The pointer
- * stays valid until the thread's next library call. */
+ * stays valid until the thread's next library call.  (Library housekeeping.) */
 const char *stencil_last_error(void);
 
-/* STENCIL_VERSION of the built library. */
+/* STENCIL_VERSION of the built library (library housekeeping). */
 int stencil_version(void);
 
 #ifdef __cplusplus

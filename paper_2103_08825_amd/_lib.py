@@ -22,7 +22,7 @@ STENCIL_E_DEVICE = -4
 STAR, BOX = 0, 1
 BC_ZERO, BC_PERIODIC = 0, 1
 F64, F32, BF16, F16 = 0, 1, 2, 3
-METHOD_AUTO, METHOD_PLAIN, METHOD_FUSED, METHOD_GENERIC = 0, 1, 2, 3
+METHOD_AUTO, METHOD_PLAIN, METHOD_FUSED, METHOD_GENERIC, METHOD_TESSELLATE = 0, 1, 2, 3, 4
 MAX_DIM = 3
 
 # Every symbol include/stencil.h declares.
@@ -43,7 +43,8 @@ class StencilError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("fused_k", ctypes.c_int), ("variant", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("chunk", ctypes.c_int), ("graph", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("chunk", ctypes.c_int), ("graph", ctypes.c_int),
+                ("inplace", ctypes.c_int)]
 
 
 class PlanDesc(ctypes.Structure):
@@ -132,11 +133,13 @@ def stencil_offsets(dim: int, radius: int, kind: int):
 
 def stencil_plan_create(shape, radius: int, kind: int, coeffs, bc: int, dtype: int,
                         method: int = METHOD_AUTO, fused_k: int = 0, variant: int = 0,
-                        autotune: bool = False, chunk: int = 0, graph: bool = False) -> int:
+                        autotune: bool = False, chunk: int = 0, graph: bool = False,
+                        inplace: bool = False) -> int:
     dim = len(shape)
     sh = (ctypes.c_int64 * max(dim, 1))(*[int(s) for s in shape])
     c = (ctypes.c_double * len(coeffs))(*[float(v) for v in coeffs])
-    opts = Opts(method, fused_k, variant, 1 if autotune else 0, chunk, 1 if graph else 0)
+    opts = Opts(method, fused_k, variant, 1 if autotune else 0, chunk, 1 if graph else 0,
+                1 if inplace else 0)
     out = ctypes.c_void_p()
     check(lib().stencil_plan_create(ctypes.byref(out), dim, sh, radius, kind, c, len(coeffs), bc,
                                     dtype, ctypes.byref(opts)), "stencil_plan_create")

@@ -11,12 +11,12 @@ import torch
 
 from . import _lib
 from ._lib import (BC_PERIODIC, BC_ZERO, BOX, F16, F32, F64, BF16, METHOD_AUTO, METHOD_FUSED,
-                   METHOD_GENERIC, METHOD_PLAIN, STAR)
+                   METHOD_GENERIC, METHOD_PLAIN, METHOD_TESSELLATE, STAR)
 
 TORCH_DTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}
 CODE_OF = {v: k for k, v in TORCH_DTYPE.items()}
 METHODS = {"auto": METHOD_AUTO, "plain": METHOD_PLAIN, "fused": METHOD_FUSED,
-           "generic": METHOD_GENERIC}
+           "generic": METHOD_GENERIC, "tessellate": METHOD_TESSELLATE}
 
 
 def dtype_code(dtype) -> int:
@@ -47,11 +47,14 @@ class Plan:
 
     coeffs are in canonical order (``offsets(dim, r, kind)``).  With graph=True,
     run() records its launches for an (input, output, T) triple into a HIP graph
-    on the first call and replays it while later calls repeat the triple."""
+    on the first call and replays it while later calls repeat the triple.  With
+    inplace=True the passes update the output field in place (no ping-pong field;
+    run(x, T, out=x) needs no copy of x)."""
 
     def __init__(self, shape: Sequence[int], r: int, kind: int, coeffs, bc: int, dtype,
                  method: str | int = "auto", fused_k: int = 0, variant: int = 0,
-                 autotune: bool = False, chunk: int = 0, graph: bool = False):
+                 autotune: bool = False, chunk: int = 0, graph: bool = False,
+                 inplace: bool = False):
         self.shape = tuple(int(s) for s in shape)
         self.r, self.kind, self.bc = int(r), int(kind), int(bc)
         self.dtype_code = dtype_code(dtype)
@@ -60,7 +63,7 @@ class Plan:
         m = METHODS[method] if isinstance(method, str) else int(method)
         self.handle = _lib.stencil_plan_create(self.shape, self.r, self.kind, self.coeffs, self.bc,
                                                self.dtype_code, m, int(fused_k), int(variant),
-                                               autotune, int(chunk), bool(graph))
+                                               autotune, int(chunk), bool(graph), bool(inplace))
         self.numel = 1
         for s in self.shape:
             self.numel *= s

@@ -6,10 +6,16 @@
 // and dL/du_0 = lambda_0.  The mirrored stencil is the plan's own stencil with
 // the weight of offset o moved to -o, run by the same sweep kernels.  Forward
 // states come from checkpoints every `ckpt` steps (the fused sweep) and are
-// rebuilt one step at a time per segment.  The coefficient sums run in
-// LDS-tiled kernels (an untiled kernel covers grids with an axis shorter than
-// the offsets' reach) whose workgroups keep their own FP64 partial slots
-// across all steps (fixed order, no atomics); one fold at the end.
+// rebuilt per segment, several steps per launch where a level-storing fused
+// pass is compiled (every intermediate level stored), else one step at a time.  Where a fused adjoint pass is
+// compiled for the stencil (2D and 3D, FP32 and FP64), the backward steps of a
+// segment run k per launch with the coefficient sums folded into the mirrored
+// sweep (stream_kernel.hpp, kAdjoint): each wave keeps FP64 sums per offset
+// and adds them to its own partial row at the end of every launch.  Otherwise
+// the sums run in LDS-tiled kernels (an untiled kernel covers grids with an
+// axis shorter than the offsets' reach) whose workgroups keep their own FP64
+// partial slots across all steps.  Either way: fixed order, no atomics, one
+// fold at the end.
 #include <algorithm>
 #include <cstdlib>
 #include <map>
@@ -20,6 +26,7 @@
 #include "device_common.hpp"
 #include "plan.hpp"
 #include "registry.hpp"
+#include "variants.hpp"
 
 namespace stn {
 
@@ -467,6 +474,63 @@ static int one_step(stencil_plan *p, const Exec &ex, const std::vector<double> &
     return STENCIL_OK;
 }
 
+// The fused adjoint pass (mirrored steps with the gradient folded in, kA
+// steps per launch) where one is compiled for the plan's stencil: the first
+// variant that has one, at its deepest compiled depth.
+struct FusedAdjoint {
+    int variant, k, chunk;
+    int64_t rows;  // gradient partial rows (the most any of its launches writes)
+};
+static bool fused_adjoint_choice(const stencil_plan *p, FusedAdjoint *out) {
+    if (p->dim < 2 || (p->dtype != STENCIL_F32 && p->dtype != STENCIL_F64)) return false;
+    const int box = p->kind == STENCIL_BOX ? 1 : 0;
+    const int nv = p->dim == 3 ? kNumV3 : kNumV2;
+    for (int v = 1; v <= nv; ++v) {
+        const int k = registered_max_k(p->dtype, p->dim, p->r, box, v, 3);
+        const VariantShape vs = p->dim == 3 ? kV3[v] : kV2[v];
+        if (k < 1) continue;
+        if (p->n1 * p->n2 * elem_bytes(p->dtype) >= ((int64_t)1 << 31) || p->n0 >= ((int64_t)1 << 31)) return false;
+        if (vs.vx > 1 && p->n2 % vs.vx) continue;
+        // balanced over the workgroups the device holds at once (the pass holds
+        // about 200 registers per lane: one workgroup per compute unit)
+        const int chunk =
+            balanced_chunk(p->dim, p->r, k, vs, p->n0, p->n1, p->n2, resident_blocks(KernelKey{p->dtype, p->dim, p->r, box, v, k, 3}));
+        int64_t rows = 0;
+        for (int kk = 1; kk <= k; ++kk)
+            rows = std::max(rows, adjoint_part_rows(p->dim, p->r, kk, vs, p->n0, p->n1, p->n2, chunk));
+        if (rows <= 0) return false;
+        *out = FusedAdjoint{v, k, chunk, rows};
+        return true;
+    }
+    return false;
+}
+
+constexpr int kMaxLevelsK = 8;  // deepest level-storing pass the recompute uses
+
+// The level-storing forward pass for a segment's recompute, where one is
+// compiled: (variant, deepest k) and, per depth, the chunk balanced over the
+// workgroups the device holds at once; k = 0 when none.
+static void levels_choice(const stencil_plan *p, int *variant, int *k, int (&chunk)[kMaxLevelsK + 1]) {
+    *variant = 0;
+    *k = 0;
+    for (int &c : chunk) c = 0;
+    if (p->dim < 2) return;
+    const int box = p->kind == STENCIL_BOX ? 1 : 0;
+    const int nv = p->dim == 3 ? kNumV3 : kNumV2;
+    for (int v = 1; v <= nv; ++v) {
+        const int kk = registered_max_k(p->dtype, p->dim, p->r, box, v, 4);
+        const VariantShape vs = p->dim == 3 ? kV3[v] : kV2[v];
+        if (kk < 2 || (vs.vx > 1 && p->n2 % vs.vx)) continue;
+        if (p->n1 * p->n2 * elem_bytes(p->dtype) >= ((int64_t)1 << 31) || p->n0 >= ((int64_t)1 << 31)) return;
+        *variant = v;
+        *k = std::min(kk, kMaxLevelsK);
+        for (int j = 2; j <= *k; ++j)
+            chunk[j] = balanced_chunk(p->dim, p->r, j, vs, p->n0, p->n1, p->n2,
+                                      resident_blocks(KernelKey{p->dtype, p->dim, p->r, box, v, j, 4}));
+        return;
+    }
+}
+
 static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const void *d_u0, const void *d_gT, int64_t T,
                         int64_t C, void *d_gu, double *d_gc, hipStream_t st) {
     const size_t field = (size_t)p->points * elem_bytes(p->dtype);
@@ -494,7 +558,10 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
     // the caller's pointers assumes workspace fields at least as aligned)
     const int64_t nck = nseg - 1, nst = seglen - 1;
     const size_t fstride = (field + 255) & ~(size_t)255;
-    const size_t part_bytes = (size_t)kGradBlocks * p->npts * sizeof(double);
+    FusedAdjoint fa{0, 0, 0, 0};
+    const bool fused = fused_adjoint_choice(p, &fa);
+    const int64_t prow = fused ? fa.rows : kGradBlocks;  // partial rows of npts doubles
+    const size_t part_bytes = (size_t)prow * p->npts * sizeof(double);
     const size_t tab_bytes = off3m.size() * sizeof(int);
     const size_t ws_bytes = (size_t)(nck + nst + 2) * fstride + part_bytes + tab_bytes;
     char *ws = nullptr;
@@ -511,7 +578,7 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
     };
     hipError_t e = hipMemcpyAsync(d_offm, off3m.data(), off3m.size() * sizeof(int), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return done(fail(STENCIL_E_DEVICE, "adjoint table upload: %s", hipGetErrorString(e)));
-    hipLaunchKernelGGL(fill_zero_f64, dim3(256), dim3(256), 0, st, part, (int64_t)kGradBlocks * p->npts);
+    hipLaunchKernelGGL(fill_zero_f64, dim3(256), dim3(256), 0, st, part, prow * p->npts);
 
     // forward: checkpoints u_{s C}
     for (int64_t s = 1; s < nseg && rc == STENCIL_OK; ++s) rc = run_passes(p, ex, ck(s - 1), ck(s), C, st);
@@ -524,9 +591,45 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
         auto state = [&](int64_t t) -> const void * {
             return t == tb ? ck(s) : static_cast<const void *>(seg_base + (size_t)(t - tb - 1) * fstride);
         };
-        for (int64_t t = tb + 1; t < te && rc == STENCIL_OK; ++t)
-            rc = one_step(p, ex1, p->dense, p->d_off, p->d_coef, state(t - 1), const_cast<void *>(state(t)), st);
+        int lvar = 0, lk = 0, lchunk[kMaxLevelsK + 1];
+        levels_choice(p, &lvar, &lk, lchunk);
+        for (int64_t t = tb + 1; t < te && rc == STENCIL_OK;) {
+            const int kk = (int)std::min<int64_t>(lk, te - t);
+            if (kk >= 2) {
+                // states t .. t+kk-1 in one launch: level j to state(t-1+j)
+                SweepLaunch L{state(t - 1), const_cast<void *>(state(t + kk - 1)), p->n0, p->n1, p->n2, p->bc,
+                              p->dense.data(), lchunk[kk], nullptr, {}, nullptr};
+                for (int j = 1; j < kk; ++j) L.ustate[j - 1] = state(t - 1 + j);
+                const SweepLauncher fn =
+                    find_launcher(KernelKey{p->dtype, p->dim, p->r, p->kind == STENCIL_BOX ? 1 : 0, lvar, kk, 4});
+                if (!fn) return done(fail(STENCIL_E_UNSUPPORTED, "no level-storing kernel with k=%d", kk));
+                e = fn(L, st);
+                if (e != hipSuccess) return done(fail(STENCIL_E_DEVICE, "recompute launch: %s", hipGetErrorString(e)));
+                t += kk;
+            } else {
+                rc = one_step(p, ex1, p->dense, p->d_off, p->d_coef, state(t - 1), const_cast<void *>(state(t)), st);
+                ++t;
+            }
+        }
         if (rc != STENCIL_OK) return done(rc);
+        if (fused) {
+            // kA mirrored steps per launch, each level pairing with its forward state
+            for (int64_t t = te - 1; t >= tb;) {
+                const int kk = (int)std::min<int64_t>(fa.k, t - tb + 1);
+                void *out = (t + 1 - kk == 0) ? d_gu : lam_buf[flip];
+                SweepLaunch L{lam, out, p->n0, p->n1, p->n2, p->bc, dense_m.data(), fa.chunk, nullptr, {}, part};
+                for (int j = 1; j <= kk; ++j) L.ustate[j - 1] = state(t + 1 - j);
+                const SweepLauncher fn =
+                    find_launcher(KernelKey{p->dtype, p->dim, p->r, p->kind == STENCIL_BOX ? 1 : 0, fa.variant, kk, 3});
+                if (!fn) return done(fail(STENCIL_E_UNSUPPORTED, "no fused adjoint kernel with k=%d", kk));
+                e = fn(L, st);
+                if (e != hipSuccess) return done(fail(STENCIL_E_DEVICE, "adjoint launch: %s", hipGetErrorString(e)));
+                lam = out;
+                flip ^= 1;
+                t -= kk;
+            }
+            continue;
+        }
         for (int64_t t = te - 1; t >= tb; --t) {
             e = p->dtype == STENCIL_F64 ? launch_grad<double>(p, lam, state(t), off3, part, st)
                                         : launch_grad<float>(p, lam, state(t), off3, part, st);
@@ -540,7 +643,7 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
             flip ^= 1;
         }
     }
-    hipLaunchKernelGGL(coeff_grad_fold, dim3(p->npts), dim3(256), 0, st, (const double *)part, kGradBlocks, p->npts,
+    hipLaunchKernelGGL(coeff_grad_fold, dim3(p->npts), dim3(256), 0, st, (const double *)part, (int)prow, p->npts,
                        d_gc);
     e = hipGetLastError();
     if (e != hipSuccess) return done(fail(STENCIL_E_DEVICE, "gradient fold: %s", hipGetErrorString(e)));

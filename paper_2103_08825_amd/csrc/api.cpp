@@ -1,8 +1,12 @@
 // api.cpp -- the C ABI: plans, sweeps, autotuning, reductions, errors.
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -99,9 +103,26 @@ static bool variant_fits_ptr(const stencil_plan *p, int variant, const void *a, 
     return v.vx == 1 || (((uintptr_t)a % al) == 0 && ((uintptr_t)b % al) == 0);
 }
 
-SweepLauncher pass_launcher(const stencil_plan *p, const Exec &ex, int k) {
+SweepLauncher pass_launcher(const stencil_plan *p, const Exec &ex, int k, bool in_place) {
     if (ex.method == STENCIL_METHOD_GENERIC) return nullptr;
-    return find_launcher(KernelKey{p->dtype, p->dim, p->r, box_key(p), ex.variant, k});
+    const int mode = ex.method == STENCIL_METHOD_TESSELLATE ? 1 : (in_place ? 2 : 0);
+    return find_launcher(KernelKey{p->dtype, p->dim, p->r, box_key(p), ex.variant, k, mode});
+}
+
+static int inplace_max_k(const stencil_plan *p, int variant) {
+    return registered_max_k(p->dtype, p->dim, p->r, box_key(p), variant, 2);
+}
+
+// side-buffer bytes of an in-place plan: the largest over the depths its passes use
+static int64_t inplace_side_bytes(const stencil_plan *p, const Exec &ex) {
+    VariantShape v;
+    if (!shape_of(p->dim, ex.variant, &v)) return 0;
+    int64_t best = 0;
+    for (int k = 1; k <= ex.k; ++k) {
+        const InplaceSide s = inplace_side(p->dim, p->r, k, v, p->n0, p->n1, p->n2, ex.chunk);
+        if (s.ok) best = std::max(best, s.total * elem_bytes(p->dtype));
+    }
+    return best;
 }
 
 // chunk 0 ("automatic") of a fused 2D/3D launch: balanced over the workgroups
@@ -144,7 +165,9 @@ static int default_k(const stencil_plan *p, int variant) {
 // Measured defaults (MI355X, 512^3 3D and 8192^2 2D grids; each the fastest
 // (variant, k, chunk) of a sweep over all compiled choices; chunk 0 = balanced
 // over the resident workgroups for the plan's shape).  stencil_autotune
-// refines them for a given plan.
+// refines them for a given plan.  The 3D 7-point FP32 depth is k = 6 since the
+// zero halo goes through the weights (sustained T = 64 sweeps, alternating
+// choices on one GPU: k = 6 2168, k = 5 2103, k = 4 1780 GStencil/s).
 struct Choice {
     int dim, r, kind, dclass;  // dclass: 0 FP64, 1 FP32, 2 16-bit
     int variant, k, chunk;     // fused
@@ -152,7 +175,7 @@ struct Choice {
 };
 static const Choice kChoices[] = {
     // 3D FP32: 7-point, 27-point, 13-point
-    {3, 1, STENCIL_STAR, 1, 5, 5, 0, 3, 8}, {3, 1, STENCIL_BOX, 1, 5, 3, 0, 5, 0},
+    {3, 1, STENCIL_STAR, 1, 5, 6, 0, 3, 8}, {3, 1, STENCIL_BOX, 1, 5, 3, 0, 5, 0},
     {3, 2, STENCIL_STAR, 1, 4, 2, 64, 5, 0},
     // 3D 16-bit storage
     {3, 1, STENCIL_STAR, 2, 5, 6, 0, 5, 0}, {3, 1, STENCIL_BOX, 2, 4, 3, 64, 4, 0},
@@ -174,10 +197,13 @@ static const Choice *measured_choice(const stencil_plan *p) {
 // The measured one-step (k = 1) choices were made on 512^3 grids.  One-step
 // launches wait on memory and want many waves in flight, so a 3D grid of fewer
 // than kPlainSmallGrid points (half of 512^3) takes the smallest tile (1,4,8)
-// with chunks of at most 8 planes instead (measured at 256^3 FP32: 7-point
-// 38 -> 29 us per step, 27-point 70 -> 46 us, 13-point 53 -> 40 us; BF16 7-point
-// 39 -> 32 us; at 384^3 FP32 7-point 128 -> 115 us; at 128^3 FP64 7-point, chunks
-// of 32 -> 8 planes: 77 -> 118 GStencil/s).
+// instead.  A measured one-step chunk above 8 planes (the 7-point stencils'
+// 32) drops to 8; a choice that leaves the chunk to the automatic rule keeps
+// that rule's shortest chunk, 4(2r+1) planes at k = 1 (12 for the 27-point box,
+// 20 for the 13-point star).  Measured so at 256^3 FP32: 7-point 38 -> 29 us per
+// step, 27-point 70 -> 46 us, 13-point 53 -> 40 us; BF16 7-point 39 -> 32 us; at
+// 384^3 FP32 7-point 128 -> 115 us; at 128^3 FP64 7-point, chunks of 32 -> 8
+// planes: 77 -> 118 GStencil/s.
 constexpr int64_t kPlainSmallGrid = (int64_t)1 << 26;
 
 static void plain_choice(const stencil_plan *p, const Choice *mc, int *variant, int *chunk) {
@@ -189,11 +215,55 @@ static void plain_choice(const stencil_plan *p, const Choice *mc, int *variant, 
     if (*chunk > 8) *chunk = 8;
 }
 
+// rows of the stage-A frame of a tessellated pass with this variant
+static int tess_tile_rows(const stencil_plan *p, int variant) {
+    VariantShape v;
+    return shape_of(p->dim, variant, &v) ? v.nw * v.rw : 0;
+}
+
+static int tess_max_k(const stencil_plan *p, int variant) {
+    return registered_max_k(p->dtype, p->dim, p->r, box_key(p), variant, 1);
+}
+
+// The tessellated method: the fused choice's variant and depth where a
+// tessellated kernel exists for them, the y extent permitting.
+static int resolve_tess(stencil_plan *p, const Choice *mc, Exec *out) {
+    const stencil_opts &o = p->opts;
+    if (p->dim != 3) return fail(STENCIL_E_UNSUPPORTED, "the tessellated sweep is built for 3D grids");
+    int variant = o.variant;
+    if (variant == 0) {
+        if (mc && tess_max_k(p, mc->variant) > 0) variant = mc->variant;
+        for (int v = 1; v <= num_variants_of(p->dim) && variant == 0; ++v)
+            if (tess_max_k(p, v) > 0) variant = v;
+    }
+    const int kmax = variant > 0 ? tess_max_k(p, variant) : 0;
+    if (kmax == 0 || !variant_fits_shape(p, variant))
+        return fail(STENCIL_E_UNSUPPORTED, "no tessellated kernel is compiled for this stencil (%dD r=%d %s dtype %d)",
+                    p->dim, p->r, p->kind == STENCIL_BOX ? "box" : "star", p->dtype);
+    int k = o.fused_k;
+    if (k == 0) k = std::min(kmax, (mc && mc->variant == variant) ? mc->k : default_k(p, variant));
+    if (k > kmax) return fail(STENCIL_E_UNSUPPORTED, "fused_k=%d exceeds the compiled tessellated maximum %d", k, kmax);
+    const int rows = tess_tile_rows(p, variant);
+    if (!tess_tiling(p->r, k, rows, p->n1, p->bc).ok)
+        return fail(STENCIL_E_UNSUPPORTED, "the tessellated sweep needs a y extent of at least %d rows (got %lld)",
+                    2 * (k + 1) * p->r, (long long)p->n1);
+    int chunk = o.chunk;
+    if (chunk == 0 && mc && mc->variant == variant) chunk = mc->chunk;
+    *out = Exec{STENCIL_METHOD_TESSELLATE, variant, k, chunk > 0 ? chunk : auto_chunk(p, variant, k)};
+    return STENCIL_OK;
+}
+
 // Resolve the requested method into an execution choice.  Returns a status.
 static int resolve_exec(stencil_plan *p) {
     const stencil_opts &o = p->opts;
     Exec ex{STENCIL_METHOD_GENERIC, 0, 1, 0};
     int method = o.method;
+    if (method == STENCIL_METHOD_TESSELLATE) {
+        if (o.inplace) return fail(STENCIL_E_UNSUPPORTED, "the tessellated method has no in-place form");
+        return resolve_tess(p, measured_choice(p), &p->exec);
+    }
+    if (o.inplace && (method == STENCIL_METHOD_GENERIC || p->dim == 1))
+        return fail(STENCIL_E_UNSUPPORTED, "in-place passes need the 2D/3D fused kernels");
     if (method == STENCIL_METHOD_AUTO) {
         method = default_variant(p, 1) ? STENCIL_METHOD_FUSED : STENCIL_METHOD_GENERIC;
     }
@@ -251,6 +321,17 @@ static int resolve_exec(stencil_plan *p) {
     ex.variant = variant;
     ex.k = k;
     ex.chunk = chunk > 0 ? chunk : auto_chunk(p, variant, k);
+    if (o.inplace && inplace_max_k(p, ex.variant) < ex.k) {
+        // the in-place pass is compiled for fewer variants: the widest that is
+        int alt = 0;
+        for (int v = 1; v <= num_variants_of(p->dim) && alt == 0; ++v)
+            if (inplace_max_k(p, v) >= ex.k && variant_fits_shape(p, v) && (o.variant == 0 || v == o.variant))
+                alt = v;
+        if (alt == 0)
+            return fail(STENCIL_E_UNSUPPORTED, "no in-place kernel is compiled for this stencil at k=%d", ex.k);
+        ex.variant = alt;
+        ex.chunk = chunk > 0 ? chunk : auto_chunk(p, alt, ex.k);
+    }
     p->exec = ex;
     return STENCIL_OK;
 }
@@ -265,12 +346,82 @@ static std::map<std::string, Exec> &tune_cache() {
     static std::map<std::string, Exec> m;
     return m;
 }
+// The tuned choice depends on the device architecture, the stencil, the grid
+// and every option that narrows the candidates (method, depth, variant, chunk).
+static std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');  // drop feature suffixes (":sramecc+:xnack-")
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
 static std::string signature(const stencil_plan *p) {
-    char buf[256];
-    snprintf(buf, sizeof buf, "d%d r%d k%d bc%d t%d m%d %lld %lld %lld", p->dim, p->r, p->kind, p->bc,
-             p->dtype, p->opts.method, (long long)p->shape[0], (long long)p->shape[1],
+    char buf[320];
+    snprintf(buf, sizeof buf, "%s d%d r%d k%d bc%d t%d m%d fk%d v%d c%d ip%d %lld %lld %lld", device_arch().c_str(),
+             p->dim, p->r, p->kind, p->bc, p->dtype, p->opts.method, p->opts.fused_k, p->opts.variant,
+             p->opts.chunk, p->opts.inplace, (long long)p->shape[0], (long long)p->shape[1],
              (long long)p->shape[2]);
     return buf;
+}
+
+// Persisted autotune results: one "signature<TAB>method variant k chunk" line per
+// entry in the file named by STENCIL_TUNE_CACHE (unset: $XDG_CACHE_HOME or
+// ~/.cache, file paper_2103_08825_amd/autotune.txt; empty: not persisted).  A
+// missing, unreadable or corrupt file (or line) is ignored: the plan tunes again.
+static std::string tune_cache_path() {
+    const char *env = getenv("STENCIL_TUNE_CACHE");
+    if (env) return env;
+    const char *xdg = getenv("XDG_CACHE_HOME");
+    const char *home = getenv("HOME");
+    std::string dir = xdg && *xdg ? std::string(xdg) : (home && *home ? std::string(home) + "/.cache" : "");
+    return dir.empty() ? "" : dir + "/paper_2103_08825_amd/autotune.txt";
+}
+
+// An entry is used only if it names a choice the plan can run.
+static bool exec_valid_for(const stencil_plan *p, const Exec &e) {
+    if (e.method != p->exec.method || e.chunk < 0 || e.k < 1) return false;
+    if (!variant_fits_shape(p, e.variant)) return false;
+    if (p->opts.inplace) return inplace_max_k(p, e.variant) >= e.k;
+    return max_k_of(p, e.variant) >= e.k;
+}
+
+static void tune_file_load(std::map<std::string, Exec> &m) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    FILE *f = fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        char *tab = strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        Exec e{0, 0, 0, 0};
+        if (sscanf(tab + 1, "%d %d %d %d", &e.method, &e.variant, &e.k, &e.chunk) != 4) continue;
+        if (m.find(line) == m.end()) m[line] = e;
+    }
+    fclose(f);
+}
+
+static void tune_file_store(const std::map<std::string, Exec> &m) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        // create the directory chain (best effort; a failure only skips persisting)
+        std::string dir = path.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    bool ok = true;
+    for (const auto &kv : m)
+        ok = ok && fprintf(f, "%s\t%d %d %d %d\n", kv.first.c_str(), kv.second.method, kv.second.variant,
+                           kv.second.k, kv.second.chunk) > 0;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok || rename(tmp.c_str(), path.c_str()) != 0) remove(tmp.c_str());
 }
 
 int plan_prepare(stencil_plan *p, hipStream_t st) {
@@ -284,7 +435,7 @@ int plan_prepare(stencil_plan *p, hipStream_t st) {
     }
     const size_t bytes = (size_t)p->points * elem_bytes(p->dtype);
     void *s = nullptr;
-    STN_HIP(hipMalloc(&s, bytes));
+    if (!p->opts.inplace) STN_HIP(hipMalloc(&s, bytes));  // in place: no ping-pong field
     // generic-kernel tables: offsets placed on the axes of the kernel view
     // (n0, n1, n2) -- 3D (z, y, x), 2D (y, 1, x), 1D (1, 1, x) -- and weights in
     // compute precision
@@ -320,6 +471,21 @@ int plan_prepare(stencil_plan *p, hipStream_t st) {
     p->d_off = d_off;
     p->d_coef = d_coef;
     p->device = dev;
+    if (p->opts.inplace) {
+        const int64_t sb = inplace_side_bytes(p, p->exec);
+        if (sb > 0) {
+            STN_HIP(hipMalloc(&p->slope, (size_t)sb));
+            p->slope_bytes = sb;
+        }
+    }
+    if (p->exec.method == STENCIL_METHOD_TESSELLATE) {
+        const int64_t sb = tess_slope_bytes(p->r, p->exec.k, tess_tile_rows(p, p->exec.variant), p->n0, p->n1,
+                                            p->n2, p->bc, p->dtype == STENCIL_F64 ? 8 : 4);
+        if (sb > 0) {
+            STN_HIP(hipMalloc(&p->slope, (size_t)sb));
+            p->slope_bytes = sb;
+        }
+    }
     return STENCIL_OK;
 }
 
@@ -341,16 +507,18 @@ int plan_alloc_alias(stencil_plan *p) {
 }
 
 static int launch_pass(stencil_plan *p, const Exec &ex, int k, const void *src, void *dst,
-                       hipStream_t st) {
+                       hipStream_t st, bool in_place = false) {
     if (ex.method == STENCIL_METHOD_GENERIC) {
         const hipError_t e = launch_generic(p->dtype, src, dst, p->n0, p->n1, p->n2, p->npts, p->bc,
                                             p->d_off, p->d_coef, st);
         if (e != hipSuccess) return fail(STENCIL_E_DEVICE, "generic sweep launch: %s", hipGetErrorString(e));
         return STENCIL_OK;
     }
-    SweepLauncher fn = pass_launcher(p, ex, k);
-    if (!fn) return fail(STENCIL_E_UNSUPPORTED, "no kernel for variant %d with k=%d", ex.variant, k);
-    SweepLaunch L{src, dst, p->n0, p->n1, p->n2, p->bc, p->dense.data(), ex.chunk};
+    SweepLauncher fn = pass_launcher(p, ex, k, in_place);
+    if (!fn)
+        return fail(STENCIL_E_UNSUPPORTED, "no %skernel for variant %d with k=%d", in_place ? "in-place " : "",
+                    ex.variant, k);
+    SweepLaunch L{src, dst, p->n0, p->n1, p->n2, p->bc, p->dense.data(), ex.chunk, p->slope};
     const hipError_t e = fn(L, st);
     if (e != hipSuccess) return fail(STENCIL_E_DEVICE, "fused sweep launch (k=%d): %s", k, hipGetErrorString(e));
     return STENCIL_OK;
@@ -366,6 +534,19 @@ int run_passes(stencil_plan *p, const Exec &ex, const void *src, void *dst, int6
     const int64_t full = T / kk;
     const int rem = (int)(T % kk);
     const int64_t P = full + (rem ? 1 : 0);
+    if (p->opts.inplace) {
+        if (ex.method == STENCIL_METHOD_GENERIC)  // no ping-pong field to fall back on
+            return fail(STENCIL_E_UNSUPPORTED, "in-place plan: the buffers' alignment forbids the plan's kernels");
+        // the first pass moves src into dst (unless they coincide), the others
+        // update dst in place
+        for (int64_t i = 1; i <= P; ++i) {
+            const int k = (i <= full) ? kk : rem;
+            const void *from = (i == 1) ? src : dst;
+            const int rc = launch_pass(p, ex, k, from, dst, st, from == dst);
+            if (rc != STENCIL_OK) return rc;
+        }
+        return STENCIL_OK;
+    }
     // buffers: b_0 = src, b_P = dst, b_i alternates dst / scratch backwards from P
     const void *cur = src;
     for (int64_t i = 1; i <= P; ++i) {
@@ -441,15 +622,24 @@ static int time_exec(stencil_plan *p, const Exec &ex, hipStream_t st, float *ms_
 }
 
 static int autotune_impl(stencil_plan *p, hipStream_t st) {
-    if (p->exec.method == STENCIL_METHOD_GENERIC) {
+    // the generic kernel has nothing to choose; the tessellated method and
+    // in-place plans keep the measured (variant, k) (their passes need buffers
+    // sized for it)
+    if (p->exec.method == STENCIL_METHOD_GENERIC || p->exec.method == STENCIL_METHOD_TESSELLATE ||
+        p->opts.inplace) {
         p->tuned = 1;
         return STENCIL_OK;
     }
     const std::string sig = signature(p);
     {
         std::lock_guard<std::mutex> g(tune_mutex());
+        static bool loaded = false;
+        if (!loaded) {
+            tune_file_load(tune_cache());
+            loaded = true;
+        }
         auto it = tune_cache().find(sig);
-        if (it != tune_cache().end()) {
+        if (it != tune_cache().end() && exec_valid_for(p, it->second)) {
             plan_drop_graph(p);
             p->exec = it->second;
             p->tuned = 1;
@@ -495,6 +685,7 @@ static int autotune_impl(stencil_plan *p, hipStream_t st) {
     p->tuned = 1;
     std::lock_guard<std::mutex> g(tune_mutex());
     tune_cache()[sig] = best;
+    tune_file_store(tune_cache());
     return STENCIL_OK;
 }
 
@@ -554,7 +745,7 @@ int stencil_plan_create(stencil_plan **out, int dim, const int64_t *shape, int r
         points *= shape[i];
     }
     if (opts) {
-        if (opts->method < STENCIL_METHOD_AUTO || opts->method > STENCIL_METHOD_GENERIC)
+        if (opts->method < STENCIL_METHOD_AUTO || opts->method > STENCIL_METHOD_TESSELLATE)
             return fail(STENCIL_E_INVALID, "unknown method %d", opts->method);
         if (opts->fused_k < 0) return fail(STENCIL_E_INVALID, "fused_k must be >= 0");
         if (opts->variant < 0) return fail(STENCIL_E_INVALID, "variant must be >= 0");
@@ -595,17 +786,20 @@ int stencil_plan_create(stencil_plan **out, int dim, const int64_t *shape, int r
         for (int i = 0; i < dim; ++i) idx = idx * W + (p->offsets[j * dim + i] + radius);
         p->dense[idx] = coeffs[j];
     }
-    p->opts = opts ? *opts : stencil_opts{0, 0, 0, 0, 0, 0};
+    p->opts = opts ? *opts : stencil_opts{0, 0, 0, 0, 0, 0, 0};
     p->tuned = 0;
     p->device = -1;
     p->scratch[0] = p->scratch[1] = nullptr;
     p->d_off = nullptr;
     p->d_coef = nullptr;
+    p->slope = nullptr;
+    p->slope_bytes = 0;
     p->graph = nullptr;
     p->graph_exec = nullptr;
     p->graph_in = nullptr;
     p->graph_out = nullptr;
     p->graph_T = -1;
+    p->graph_failed = 0;
     const int rc = resolve_exec(p);
     if (rc != STENCIL_OK) {
         delete p;
@@ -622,6 +816,7 @@ void stencil_plan_destroy(stencil_plan *p) {
     if (p->scratch[1]) (void)hipFree(p->scratch[1]);
     if (p->d_off) (void)hipFree(p->d_off);
     if (p->d_coef) (void)hipFree(p->d_coef);
+    if (p->slope) (void)hipFree(p->slope);
     delete p;
 }
 
@@ -651,10 +846,11 @@ int stencil_plan_info(const stencil_plan *p, stencil_plan_desc *out) {
             out->tile[0] = g.out_x;
             out->tile[1] = p->dim == 3 ? g.out_y : 0;
             out->tile[2] = p->dim >= 2 ? g.chunk : 0;
+            if (p->exec.method == STENCIL_METHOD_TESSELLATE) out->tile[1] = v.nw * v.rw;  // y tile rows
         }
     }
     const int64_t field = p->points * elem_bytes(p->dtype);
-    out->scratch_bytes = (p->scratch[0] ? field : 0) + (p->scratch[1] ? field : 0);
+    out->scratch_bytes = (p->scratch[0] ? field : 0) + (p->scratch[1] ? field : 0) + p->slope_bytes;
     out->tuned = p->tuned;
     return STENCIL_OK;
 }
@@ -683,14 +879,15 @@ int stencil_run(stencil_plan *p, const void *d_in, void *d_out, int64_t T, void 
         rc = autotune_impl(p, st);
         if (rc != STENCIL_OK) return rc;
     }
-    if (d_in == d_out && T > 0) {
+    const bool copy_alias = d_in == d_out && T > 0 && !p->opts.inplace;
+    if (copy_alias) {
         rc = plan_alloc_alias(p);
         if (rc != STENCIL_OK) return rc;
     }
     // enqueue the whole sweep on `s` (the caller's stream, or a capture stream)
     auto enqueue = [&](hipStream_t s) -> int {
         const void *src = d_in;
-        if (d_in == d_out && T > 0) {
+        if (copy_alias) {
             STN_HIP(hipMemcpyAsync(p->scratch[1], d_in, (size_t)p->points * elem_bytes(p->dtype),
                                    hipMemcpyDeviceToDevice, s));
             src = p->scratch[1];
@@ -698,31 +895,37 @@ int stencil_run(stencil_plan *p, const void *d_in, void *d_out, int64_t T, void 
         const Exec ex = exec_for_ptrs(p, src, d_out);
         return run_passes(p, ex, src, d_out, T, s);
     };
-    if (!p->opts.graph || T == 0) return enqueue(st);
+    if (!p->opts.graph || T == 0 || p->graph_failed) return enqueue(st);
     if (!(p->graph_exec && p->graph_in == d_in && p->graph_out == d_out && p->graph_T == T)) {
         // record on a private stream: the caller's stream may be the legacy default
-        // stream, which cannot be captured; the launches depend on nothing else
+        // stream, which cannot be captured; the launches depend on nothing else.
+        // If capturing or instantiating fails, nothing was enqueued: the plan
+        // stops recording and runs the sweep with direct launches.
         plan_drop_graph(p);
         hipStream_t cap = nullptr;
         STN_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
             (void)hipStreamDestroy(cap);
-            return fail(STENCIL_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+            (void)hipGetLastError();
+            p->graph_failed = 1;
+            return enqueue(st);
         }
         rc = enqueue(cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cap, &g);
         (void)hipStreamDestroy(cap);
-        if (rc != STENCIL_OK) {
+        if (rc != STENCIL_OK && e == hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
-            return rc;
+            return rc;  // an argument or launch error, not a capture failure
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             p->graph_exec = nullptr;
-            return fail(STENCIL_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+            (void)hipGetLastError();
+            p->graph_failed = 1;
+            return enqueue(st);
         }
         p->graph = g;
         p->graph_in = d_in;

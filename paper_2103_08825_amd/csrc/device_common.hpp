@@ -31,6 +31,11 @@ template <typename S> __device__ __forceinline__ S from_compute(double v);
 template <> __device__ __forceinline__ float from_compute<float>(float v) { return v; }
 template <> __device__ __forceinline__ double from_compute<double>(double v) { return v; }
 template <> __device__ __forceinline__ _Float16 from_compute<_Float16>(float v) {
+    // The empty asm makes the FP32 value opaque, so the compiler cannot fuse the
+    // FMA that produced it with this conversion (v_fma_mixlo_f16 rounds the exact
+    // a*b+c straight to FP16): every result is rounded to FP32 first, then to
+    // FP16, wherever the kernel stores it.
+    asm("" : "+v"(v));
     return (_Float16)v;  // v_cvt_f16_f32, round to nearest even
 }
 template <> __device__ __forceinline__ bf16_t from_compute<bf16_t>(float v) {
@@ -216,6 +221,38 @@ template <int S> __device__ __forceinline__ void dpp_fmac1(float c, const float 
             : "v"(x[0]), "v"(c));
     }
 }
+
+// acc += (x[i] held by lane l + S) * u[i] for i = 0 .. N-1 in that order: one
+// accumulator, the lane-shifted operand a DPP source as in fma_shift_rows (a
+// source lane outside the wave reads 0).  The instructions of a block write
+// only acc, which no DPP operand reads, so one s_nop per block covers the
+// hazard on the x registers.
+template <int S, int N> __device__ __forceinline__ void dpp_fmac_chain(const float (&u)[N], const float (&x)[N], float &acc) {
+    static_assert(S == -1 || S == 1, "one-lane shift");
+    constexpr int N4 = N / 4 * 4;
+#pragma unroll
+    for (int b = 0; b < N4; b += 4) {
+        if constexpr (S == -1)
+            asm("s_nop 1\n\t" STN_DPP_FMAC("%0", "%1", "%5", "wave_shr:1") STN_DPP_FMAC("%0", "%2", "%6", "wave_shr:1")
+                    STN_DPP_FMAC("%0", "%3", "%7", "wave_shr:1") STN_DPP_FMAC("%0", "%4", "%8", "wave_shr:1")
+                : "+v"(acc)
+                : "v"(x[b]), "v"(x[b + 1]), "v"(x[b + 2]), "v"(x[b + 3]), "v"(u[b]), "v"(u[b + 1]), "v"(u[b + 2]),
+                  "v"(u[b + 3]));
+        else
+            asm("s_nop 1\n\t" STN_DPP_FMAC("%0", "%1", "%5", "wave_shl:1") STN_DPP_FMAC("%0", "%2", "%6", "wave_shl:1")
+                    STN_DPP_FMAC("%0", "%3", "%7", "wave_shl:1") STN_DPP_FMAC("%0", "%4", "%8", "wave_shl:1")
+                : "+v"(acc)
+                : "v"(x[b]), "v"(x[b + 1]), "v"(x[b + 2]), "v"(x[b + 3]), "v"(u[b]), "v"(u[b + 1]), "v"(u[b + 2]),
+                  "v"(u[b + 3]));
+    }
+#pragma unroll
+    for (int i = N4; i < N; ++i) {
+        if constexpr (S == -1)
+            asm("s_nop 1\n\t" STN_DPP_FMAC("%0", "%1", "%2", "wave_shr:1") : "+v"(acc) : "v"(x[i]), "v"(u[i]));
+        else
+            asm("s_nop 1\n\t" STN_DPP_FMAC("%0", "%1", "%2", "wave_shl:1") : "+v"(acc) : "v"(x[i]), "v"(u[i]));
+    }
+}
 #undef STN_DPP_FMAC
 
 template <int S, int N> __device__ __forceinline__ void fma_shift_rows(float c, const float (&x)[N], float (&t)[N]) {
@@ -238,6 +275,21 @@ template <int S, int N> __device__ __forceinline__ void fma_shift_rows(double c,
     for (int i = 0; i < N; ++i) t[i] = fma_c(c, lane_shift<S>(x[i]), t[i]);
 }
 
+
+// Masks built with integer arithmetic (-1 = true, 0 = false), so wave-uniform
+// tests stay in scalar registers: a comparison turned into a bool becomes a
+// lane mask, and selecting with it costs a vector instruction per use.
+__device__ __forceinline__ int mask_lt(int a, int b) { return (a - b) >> 31; }  // a < b (no overflow)
+__device__ __forceinline__ int mask_in(int v, int n) { return ~((v | (n - 1 - v)) >> 31); }  // 0 <= v < n
+// bitwise OR of two values (one of them +0.0): the other value, exactly
+__device__ __forceinline__ float bits_or(float a, float b) { return __int_as_float(__float_as_int(a) | __float_as_int(b)); }
+__device__ __forceinline__ double bits_or(double a, double b) {
+    return __longlong_as_double(__double_as_longlong(a) | __double_as_longlong(b));
+}
+__device__ __forceinline__ float weight_if(float c, int mask) { return __int_as_float(__float_as_int(c) & mask); }
+__device__ __forceinline__ double weight_if(double c, int mask) {
+    return __longlong_as_double(__double_as_longlong(c) & (long long)mask);  // mask sign-extends
+}
 
 constexpr int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 constexpr int posmod(int a, int b) { return ((a % b) + b) % b; }

@@ -18,6 +18,19 @@ template <typename C> struct StreamArgs {
     int halo_x;            // x halo of the widened tile (>= K*R, multiple of VX)
     int bc;                // 0 zero halo, 1 periodic
     int nblocks;           // launched workgroups
+    // tessellated stages only: y tiles of tile_h rows (the last starts at
+    // last_start), ncut cuts, slope buffer in compute precision
+    int tile_h, last_start, ncut;
+    void *slope;           // tessellated: slope buffer; in place: side buffer
+    // in place only: side-buffer elements per band block and per whole-plane
+    // block, offset of the whole-plane blocks, x tiles per workgroup
+    int64_t side_band, side_zplane, side_z0;
+    int side_nw;
+    // fused adjoint only: the forward state each level pairs with (level j:
+    // ustate[j-1]) and the FP64 gradient partials, one row of npts per wave
+    const void *ustate[8];
+    double *gpart;
+    int npts;
     C coef[kMaxDense];     // dense weight table, [dz][dy][dx] in 3D, [dz][dx] in 2D
 };
 

@@ -18,6 +18,9 @@ struct SweepLaunch {
     int bc;
     const double *dense; // dense weight table: [dz][dy][dx] (3D), [dz][dx] (2D), [dx] (1D)
     int chunk;           // planes per workgroup along axis 0; 0 = automatic
+    void *aux;           // tessellated sweeps: the slope buffer (tess_slope_bytes)
+    const void *ustate[8];  // fused adjoint: forward state of each level (level j: [j-1])
+    double *gpart;          // fused adjoint: gradient partials (adjoint_part_rows rows of npts)
 };
 
 using SweepLauncher = hipError_t (*)(const SweepLaunch &, hipStream_t);
@@ -92,6 +95,71 @@ inline int balanced_chunk(int dim, int r, int k, VariantShape v, int64_t n0, int
         }
     }
     return (int)best_c;
+}
+
+// y tiling of a tessellated 3D sweep: tiles of `tile_h` rows (the stage-A
+// frame), the last starting at last_start; every tile must hold at least
+// 2(K+1)R rows (its trapezoid and both slopes), so a short remainder is merged
+// with the tile before it and the pair split in two.
+struct TessTiling {
+    int tile_h, tiles_y, last_start, ncut;
+    bool ok;
+};
+inline TessTiling tess_tiling(int r, int k, int tile_h, int64_t n1, int bc) {
+    TessTiling t{tile_h, 0, 0, 0, false};
+    const int64_t need = 2 * (int64_t)(k + 1) * r;
+    if (tile_h < need || n1 < need || n1 > 0x7fffffff) return t;
+    int64_t tiles = (n1 + tile_h - 1) / tile_h;
+    int64_t last = (tiles - 1) * tile_h;
+    if (n1 - last < need) {
+        if (tiles == 1) return t;
+        // the last two tiles share their rows evenly
+        const int64_t a = (tiles - 2) * tile_h;
+        last = a + (n1 - a + 1) / 2;
+        if (last - a < need || n1 - last < need) return t;
+    }
+    t.tiles_y = (int)tiles;
+    t.last_start = (int)last;
+    t.ncut = (int)tiles + (bc == 0 ? 1 : 0);  // the zero halo also cuts at n1
+    t.ok = true;
+    return t;
+}
+
+// slope buffer of a tessellated pass of k steps (compute-type elements)
+inline int64_t tess_slope_bytes(int r, int k, int tile_h, int64_t n0, int64_t n1, int64_t n2, int bc,
+                                int elem) {
+    const TessTiling t = tess_tiling(r, k, tile_h, n1, bc);
+    if (!t.ok || k < 2) return 0;
+    return (int64_t)(k - 1) * t.tiles_y * 2 * n0 * 2 * r * n2 * elem;
+}
+
+// Rows of FP64 gradient partials a fused adjoint launch writes (one per wave).
+inline int64_t adjoint_part_rows(int dim, int r, int k, VariantShape v, int64_t n0, int64_t n1, int64_t n2,
+                                 int chunk) {
+    const Geometry g = stream_geometry(dim, r, k, v, n0, n1, n2, chunk);
+    return g.ok ? (int64_t)g.nblocks * v.nw : 0;
+}
+
+// Side buffer of one in-place pass (storage-type elements): per band block
+// (one per workgroup and output plane; 2D: per wave) the band points of the
+// output tile, then per whole-plane block (2*K*R per workgroup) a full tile.
+struct InplaceSide {
+    int64_t band, zplane, z0, total;
+    bool ok;
+};
+inline InplaceSide inplace_side(int dim, int r, int k, VariantShape v, int64_t n0, int64_t n1, int64_t n2,
+                                int chunk) {
+    InplaceSide s{0, 0, 0, 0, false};
+    const Geometry g = stream_geometry(dim, r, k, v, n0, n1, n2, chunk);
+    if (!g.ok) return s;
+    const int64_t subs = dim == 3 ? g.nblocks : (int64_t)g.nblocks * v.nw;
+    const int64_t kr = (int64_t)k * r;
+    s.band = dim == 3 ? 2 * kr * g.out_x + (int64_t)g.out_y * 2 * g.halo_x : 2 * (int64_t)g.halo_x;
+    s.zplane = dim == 3 ? (int64_t)g.out_x * g.out_y : g.out_x;
+    s.z0 = subs * g.chunk * s.band;
+    s.total = s.z0 + subs * 2 * kr * s.zplane;
+    s.ok = true;
+    return s;
 }
 
 inline Geometry seg1d_geometry(int r, int k, VariantShape v, int64_t n) {

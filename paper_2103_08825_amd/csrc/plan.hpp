@@ -52,6 +52,8 @@ struct stencil_plan {
     // device state (bound to one device at prepare time)
     int device;
     void *scratch[2];               // [0] ping-pong field, [1] copy of an aliased input
+    void *slope;                    // tessellated passes: slope rows; in-place passes: side buffer
+    int64_t slope_bytes;
     int *d_off;                     // generic kernel tables
     void *d_coef;
     // recorded launches of one (d_in, d_out, T) triple (opts.graph)
@@ -60,6 +62,7 @@ struct stencil_plan {
     const void *graph_in;
     void *graph_out;
     int64_t graph_T;
+    int graph_failed;               // capture failed once: run with direct launches
 };
 
 namespace stn {
@@ -75,8 +78,9 @@ Exec exec_for_ptrs(const stencil_plan *p, const void *a, const void *b);
 Exec exec_for_ptrs(const stencil_plan *p, Exec ex, const void *a, const void *b);
 // one step per launch (the measured plain choice where there is one)
 Exec one_step_exec(const stencil_plan *p);
-// launcher of one pass of k steps under ex (nullptr if none)
-SweepLauncher pass_launcher(const stencil_plan *p, const Exec &ex, int k);
+// launcher of one pass of k steps under ex (nullptr if none); in_place: the
+// pass updates src == dst through the plan's side buffer
+SweepLauncher pass_launcher(const stencil_plan *p, const Exec &ex, int k, bool in_place = false);
 hipError_t launch_reduce(int dtype, const void *u, const void *ref, int64_t n, double *part,
                          double *out, hipStream_t st);
 int reduce_partials_bytes();

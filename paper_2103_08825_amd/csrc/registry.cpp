@@ -8,7 +8,7 @@
 namespace stn {
 namespace {
 
-using Key = std::tuple<int, int, int, int, int, int>;
+using Key = std::tuple<int, int, int, int, int, int, int>;
 
 std::mutex &reg_mutex() {
     static std::mutex m;
@@ -22,7 +22,7 @@ std::map<Key, Entry> &reg_map() {
     static std::map<Key, Entry> m;
     return m;
 }
-Key tup(const KernelKey &k) { return Key(k.dtype, k.dim, k.r, k.box, k.variant, k.k); }
+Key tup(const KernelKey &k) { return Key(k.dtype, k.dim, k.r, k.box, k.variant, k.k, k.mode); }
 
 }  // namespace
 
@@ -51,13 +51,14 @@ int resident_blocks(const KernelKey &key) {
     return cus * occ();
 }
 
-int registered_max_k(int dtype, int dim, int r, int box, int variant) {
+int registered_max_k(int dtype, int dim, int r, int box, int variant, int mode) {
     std::lock_guard<std::mutex> g(reg_mutex());
     int best = 0;
     for (const auto &kv : reg_map()) {
         const Key &k = kv.first;
         if (std::get<0>(k) == dtype && std::get<1>(k) == dim && std::get<2>(k) == r &&
-            std::get<3>(k) == box && std::get<4>(k) == variant && std::get<5>(k) > best)
+            std::get<3>(k) == box && std::get<4>(k) == variant && std::get<6>(k) == mode &&
+            std::get<5>(k) > best)
             best = std::get<5>(k);
     }
     return best;
@@ -70,7 +71,7 @@ int registered_keys(KernelKey *out, int cap) {
         if (out && n < cap) {
             const Key &k = kv.first;
             out[n] = KernelKey{std::get<0>(k), std::get<1>(k), std::get<2>(k),
-                               std::get<3>(k), std::get<4>(k), std::get<5>(k)};
+                               std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k)};
         }
         ++n;
     }

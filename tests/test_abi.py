@@ -202,3 +202,33 @@ def test_one_step_tile_follows_the_grid_size(L):
     f64 = _lib.stencil_plan_info(h)
     _lib.stencil_plan_destroy(h)
     assert f64["variant"] == 1 and f64["tile"][2] <= 8
+    # the 27-point box and the 13-point star leave the one-step chunk to the
+    # automatic rule, whose shortest chunk at k = 1 is 4(2r+1) planes
+    for r, kind, n in ((1, 1, 27), (2, 0, 13)):
+        rc, h = _create(L, (256, 256, 256), r, kind, [0.01] * n, 0, _lib.F32, method=_lib.METHOD_PLAIN)
+        assert rc == 0, _lib.last_error()
+        info = _lib.stencil_plan_info(h)
+        _lib.stencil_plan_destroy(h)
+        assert info["variant"] == 1 and info["tile"][2] == 4 * (2 * r + 1), (r, kind, info)
+
+
+def test_tessellated_plans(L):
+    # the tessellated method resolves on 3D grids with y extent >= 2(k+1)r and
+    # reports its y tile; it refuses 2D grids, short y extents and depths
+    # without a compiled kernel
+    c7 = [0.1] * 7
+    rc, h = _create(L, (512, 512, 512), 1, 0, c7, 0, _lib.F32, method=_lib.METHOD_TESSELLATE)
+    assert rc == 0, _lib.last_error()
+    info = _lib.stencil_plan_info(h)
+    _lib.stencil_plan_destroy(h)
+    assert info["method"] == _lib.METHOD_TESSELLATE and info["tile"][1] == 64
+    rc, h = _create(L, (16, 11, 64), 1, 0, c7, 0, _lib.F32, method=_lib.METHOD_TESSELLATE, fused_k=5)
+    assert rc == _lib.STENCIL_E_UNSUPPORTED and h is None
+    assert "y extent" in _lib.last_error()
+    rc, h = _create(L, (16, 12, 64), 1, 0, c7, 0, _lib.F32, method=_lib.METHOD_TESSELLATE, fused_k=5)
+    assert rc == 0, _lib.last_error()
+    _lib.stencil_plan_destroy(h)
+    rc, h = _create(L, (64, 64), 1, 0, [0.2] * 5, 0, _lib.F32, method=_lib.METHOD_TESSELLATE)
+    assert rc == _lib.STENCIL_E_UNSUPPORTED
+    rc, h = _create(L, (16, 64, 64), 1, 0, c7, 0, _lib.F32, method=_lib.METHOD_TESSELLATE, fused_k=9)
+    assert rc == _lib.STENCIL_E_UNSUPPORTED

@@ -99,16 +99,27 @@ def test_adjoint_field_beyond_2gib_matches_oracle():
     assert e_u <= TOL["f32"] and e_c <= TOL["f32"], (e_u, e_c)
 
 
-def test_adjoint_checkpoint_interval_invariance_bitwise():
-    """The recomputed states and the partial sums do not depend on the interval."""
-    shape, c, c_ex, x, u_ex, y = _setup(3, 1, 0, 0, "f32", seed=4)
-    plan = Plan(shape, 1, 0, c, 0, "f32")
-    g = torch.from_numpy(y).float().cuda()
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_adjoint_checkpoint_interval_invariance(dt):
+    """The recomputed states, and so dL/du0, do not depend on the interval (bit
+    for bit).  dL/dc is a sum of the same products in a different grouping: the
+    launches a segment takes decide which steps share a launch.  FP64 plans sum
+    the products in FP64, so the results agree to FP64 rounding.  FP32 plans sum
+    a launch's products for one stream step (at most k*4 of them per thread and
+    term, k <= 4) in FP32 before adding them to the FP64 sums, so two
+    groupings differ by the rounding of those short FP32 sums: about 2^-24 of
+    the products' magnitudes, random in sign (1.3e-8 of max|dL/dc| measured
+    here; the bound asserted is 1e-6)."""
+    shape, c, c_ex, x, u_ex, y = _setup(3, 1, 0, 0, dt, seed=4)
+    plan = Plan(shape, 1, 0, c, 0, dt)
+    g = torch.from_numpy(y).to(x.dtype).cuda()
     ref_u, ref_c = plan.adjoint(x, g, 13, 1)
+    tol_c = 1e-12 if dt == "f64" else 1e-6
     for ck in (2, 5, 13, 40):
         gu, gc = plan.adjoint(x, g, 13, ck)
         torch.cuda.synchronize()
-        assert torch.equal(gu, ref_u) and torch.equal(gc, ref_c), ck
+        assert torch.equal(gu, ref_u), ck
+        assert float((gc - ref_c).abs().max() / ref_c.abs().max()) <= tol_c, ck
 
 
 @pytest.mark.parametrize("dim,r,kind,bc", [(2, 1, 1, 1), (3, 1, 0, 0), (3, 2, 0, 1), (1, 2, 0, 0)])
