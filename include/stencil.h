@@ -219,6 +219,17 @@ int stencil_batch_info(const stencil_batch *b, int64_t *items, int64_t *workgrou
  * work item (batched extension): STENCIL_E_DEVICE if a work item gave up waiting for its
  * predecessor (a bounded wait; it cannot happen with a well-formed list). */
 int stencil_batch_status(const stencil_batch *b, void *stream);
+/* How long a work item of the batch polls for the previous pass of its grid
+ * before it gives up (batched extension, housekeeping).  limit_us: microseconds,
+ * >= 0; 0 gives up at the first wait that is not already satisfied.  The
+ * default is 1,000,000 (about one second of the device's 100 MHz clock).  A
+ * give-up sets the batch's error flag, every later wait of that replay gives up
+ * at once (the kernel still ends), and stencil_batch_status reports
+ * STENCIL_E_DEVICE; each replay starts with the flag cleared.  The value is
+ * written to device memory on `stream`, so it applies to replays launched on
+ * that stream afterwards.  Errors: STENCIL_E_INVALID for a NULL batch or a
+ * negative limit, STENCIL_E_DEVICE if the write fails. */
+int stencil_batch_set_wait_limit(stencil_batch *b, int64_t limit_us, void *stream);
 
 /* --- derivative --------------------------------------------------------------- */
 

@@ -30,7 +30,7 @@ EXPORTS = (
     "stencil_num_points", "stencil_offsets", "stencil_plan_create", "stencil_plan_destroy",
     "stencil_plan_info", "stencil_plan_prepare", "stencil_autotune", "stencil_run",
     "stencil_run_batched", "stencil_batch_create", "stencil_batch_launch", "stencil_batch_destroy",
-    "stencil_batch_info", "stencil_batch_status", "stencil_adjoint", "stencil_reduce", "stencil_reduce_noalloc", "stencil_last_error",
+    "stencil_batch_info", "stencil_batch_status", "stencil_batch_set_wait_limit", "stencil_adjoint", "stencil_reduce", "stencil_reduce_noalloc", "stencil_last_error",
     "stencil_version",
 )
 
@@ -87,6 +87,7 @@ def lib():
             "stencil_batch_destroy": (None, [vp]),
             "stencil_batch_info": (ci, [vp, P(i64), P(i64)]),
             "stencil_batch_status": (ci, [vp, vp]),
+            "stencil_batch_set_wait_limit": (ci, [vp, i64, vp]),
             "stencil_adjoint": (ci, [vp, vp, vp, i64, i64, vp, vp, vp]),
             "stencil_reduce": (ci, [ci, vp, vp, i64, vp, vp]),
             "stencil_reduce_noalloc": (ci, [ci, vp, vp, i64, vp, vp]),
@@ -204,6 +205,10 @@ def stencil_batch_info(batch: int):
 
 def stencil_batch_status(batch: int, stream: int) -> None:
     check(lib().stencil_batch_status(batch, stream), "stencil_batch_status")
+
+
+def stencil_batch_set_wait_limit(batch: int, limit_us: int, stream: int) -> None:
+    check(lib().stencil_batch_set_wait_limit(batch, int(limit_us), stream), "stencil_batch_set_wait_limit")
 
 
 def stencil_adjoint(plan: int, d_u0: int, d_gT: int, T: int, ckpt: int, d_grad_u0: int,

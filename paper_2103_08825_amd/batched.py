@@ -31,6 +31,11 @@ class Batch:
     def status(self) -> None:
         _lib.stencil_batch_status(self.handle, _stream())
 
+    def set_wait_limit(self, limit_us: int) -> None:
+        """How long an item polls for its grid's previous pass before giving up
+        (microseconds; default one second)."""
+        _lib.stencil_batch_set_wait_limit(self.handle, limit_us, _stream())
+
     def info(self):
         return _lib.stencil_batch_info(self.handle)
 

@@ -17,6 +17,7 @@
 // The counter reset and the persistent kernel are captured once into a HIP
 // graph; stencil_batch_launch replays it.
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -36,6 +37,7 @@ struct stencil_batch {
     stn::BatchArgs args;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    uint64_t wait_ticks;  // host copy of the wait limit (source of its upload)
 };
 
 namespace stn {
@@ -172,9 +174,11 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
     const size_t grids_b = align(sizeof(BatchGrid) * n);
     const size_t items_b = align(sizeof(BatchItem) * std::max<size_t>(1, items.size()));
     // counters: per grid, then the partition cursors (one line each), the error
-    // flag and the partition bounds
+    // flag (the replay's reset clears these), the partition bounds and the wait
+    // limit (8-byte aligned)
     const size_t ctr_ints = (size_t)n + kBatchParts * kCursorStride + 1;
-    const size_t ctr_b = align(sizeof(int) * (ctr_ints + kBatchParts + 1));
+    const size_t wait_off = (sizeof(int) * (ctr_ints + kBatchParts + 1) + 7) & ~(size_t)7;
+    const size_t ctr_b = align(wait_off + sizeof(uint64_t));
     size_t scratch_b = 0;
     for (int i = 0; i < n; ++i)
         if (grids[i].npass > 1) scratch_b += align((size_t)plans[i]->points * eb);
@@ -183,6 +187,7 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
     b->mem = nullptr;
     b->graph = nullptr;
     b->exec = nullptr;
+    b->wait_ticks = kDefaultWaitTicks;
     auto cleanup = [&](int code) {
         if (b->exec) (void)hipGraphExecDestroy(b->exec);
         if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -210,6 +215,8 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
     int *ctr = reinterpret_cast<int *>(base + grids_b + items_b);
     if (e == hipSuccess)
         e = hipMemcpy(ctr + ctr_ints, part_begin.data(), sizeof(int) * part_begin.size(), hipMemcpyHostToDevice);
+    uint64_t *wait_dev = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(ctr) + wait_off);
+    if (e == hipSuccess) e = hipMemcpy(wait_dev, &b->wait_ticks, sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(fail(STENCIL_E_DEVICE, "batch upload: %s", hipGetErrorString(e)));
     int rmax = 1;
     for (int i = 0; i < n; ++i) rmax = std::max(rmax, grids[i].r);
@@ -224,7 +231,7 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
     b->nitems = (int64_t)items.size();
     b->workgroups = wgs;
     b->args = BatchArgs{reinterpret_cast<const BatchGrid *>(base), reinterpret_cast<const BatchItem *>(base + grids_b),
-                        ctr + ctr_ints, ctr, ctr + n, ctr + n + kBatchParts * kCursorStride};
+                        ctr + ctr_ints, ctr, ctr + n, ctr + n + kBatchParts * kCursorStride, wait_dev};
     STN_HIP(hipGetDevice(&b->device));
     // capture: reset counters, cursor and error flag with a kernel, then the persistent kernel
     hipStream_t cap = nullptr;
@@ -294,6 +301,18 @@ int stencil_batch_status(const stencil_batch *b, void *stream) {
     int flag = 0;
     STN_HIP(hipMemcpy(&flag, b->args.error, sizeof(int), hipMemcpyDeviceToHost));
     if (flag) return fail(STENCIL_E_DEVICE, "a batched work item waited past the spin limit");
+    return STENCIL_OK;
+}
+
+int stencil_batch_set_wait_limit(stencil_batch *b, int64_t limit_us, void *stream) {
+    clear_error();
+    if (!b) return fail(STENCIL_E_INVALID, "batch is NULL");
+    if (limit_us < 0) return fail(STENCIL_E_INVALID, "negative wait limit");
+    const uint64_t cap = UINT64_MAX / kTicksPerUs;
+    b->wait_ticks = (uint64_t)limit_us > cap ? UINT64_MAX : (uint64_t)limit_us * kTicksPerUs;
+    // ordered after earlier replays on the stream; the host value stays in the batch
+    STN_HIP(hipMemcpyAsync(const_cast<uint64_t *>(b->args.wait_ticks), &b->wait_ticks, sizeof(uint64_t),
+                           hipMemcpyHostToDevice, (hipStream_t)stream));
     return STENCIL_OK;
 }
 

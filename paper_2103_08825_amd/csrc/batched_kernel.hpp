@@ -15,9 +15,11 @@ constexpr int kBatchMaxK2 = 4;  // ... for order-2 stencils
 // and a long chain of passes stays short (measured on the uneven 256-grid
 // workload: 128 beats 64, 256 and 512)
 constexpr int kBatchChunk = 128;
-// A wait gives up after this many ticks of the 100 MHz real-time counter
-// (about one second), or at once when another workgroup already gave up.
-constexpr uint64_t kWaitTicks = 100000000ull;
+// A wait gives up after a limit in ticks of the 100 MHz real-time counter
+// (stencil_batch_set_wait_limit; by default about one second), or at once when
+// another workgroup already gave up.
+constexpr uint64_t kTicksPerUs = 100;
+constexpr uint64_t kDefaultWaitTicks = 1000000ull * kTicksPerUs;
 
 struct BatchGrid {
     const void *in;
@@ -47,6 +49,7 @@ struct BatchArgs {
     int *counters;          // one per grid
     int *cursors;           // kBatchParts, kCursorStride apart
     int *error;
+    const uint64_t *wait_ticks;  // the wait limit (not cleared between replays)
 };
 
 __device__ __forceinline__ const void *pass_src(const BatchGrid &g, int p) {
@@ -141,10 +144,11 @@ __global__ void __launch_bounds__(64 * kBatchNW) batched_kernel(const BatchArgs 
             if (ipass > 0) {
                 // poll with relaxed device-coherent loads; a single acquire follows
                 const int need = ipass * g.nblk;
+                const uint64_t limit = *a.wait_ticks;
                 const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
                 while (__hip_atomic_load(a.counters + grid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                     if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-                        __builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
+                        __builtin_amdgcn_s_memrealtime() - t0 > limit) {
                         ok = 0;
                         __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         break;

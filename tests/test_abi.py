@@ -152,6 +152,7 @@ def test_batched_rejects_bad_plans_before_any_device_call(L):
     assert create([h2], [None], [32]) == _lib.STENCIL_E_INVALID
     assert out.value is None
     assert L.stencil_batch_launch(None, None) == _lib.STENCIL_E_INVALID
+    assert L.stencil_batch_set_wait_limit(None, 10, None) == _lib.STENCIL_E_INVALID
     L.stencil_batch_destroy(None)
     for h in (h3, h2, hd):
         _lib.stencil_plan_destroy(h)

@@ -157,3 +157,31 @@ def test_paper_scale_batch_equals_single_runs():
         say("  grid %d %s %s T=%d: rel err %.3e" % (i, g.shape, "box" if g.kind else "star", g.T, err))
         assert err <= 1e-5, (i, err)
     b.close()
+
+
+def test_wait_limit_gives_up_and_the_next_replay_recovers():
+    """A zero wait limit (set from the host) makes the first unsatisfied wait give
+    up: the error flag makes every later wait of that replay give up at once, the
+    kernel ends, and the batch reports a device error.  With the default limit
+    restored the next replay clears the flag and completes."""
+    rng = np.random.default_rng(9)
+    c = W.coefficients(rng, 5)
+    shape, T = (512, 512), 64  # 8 passes of 8 steps, dozens of items per pass
+    plan = Plan(shape, 1, 0, c, 0, "f32")
+    x = torch.from_numpy(rng.uniform(-1, 1, shape)).float().cuda()
+    y = torch.empty_like(x)
+    b = Batch([plan], [x], [y], [T])
+    say("wait limit 0: launching")
+    b.set_wait_limit(0)
+    b.launch()
+    with pytest.raises(StencilError):
+        b.status()
+    say("wait limit restored: launching")
+    b.set_wait_limit(1_000_000)
+    b.launch()
+    b.status()
+    torch.cuda.synchronize()
+    assert torch.equal(y, plan.run(x, T))
+    with pytest.raises(StencilError):
+        b.set_wait_limit(-1)
+    b.close()
