@@ -144,11 +144,13 @@ def launch_probe(plan, buf, k, n):
     return ms
 
 
-def bench_batched(a):
+def batched_rate(steps, compare):
     """256 independent 2D FP32 grids (sides log-uniform in [64, 2048], 5-point star
     or 9-point box, T uniform in [10, 200], zero halo): one graph-captured
-    persistent launch (library default depth and chunk) against 256 separate plain sweeps
-    (k = 1, one launch per step) and 256 separate fused sweeps."""
+    persistent launch (library default depth and chunk), optionally against 256
+    separate plain sweeps (k = 1, one launch per step) and 256 separate fused
+    sweeps.  Returns a record; hbm_frac_alg is one read and one write of every
+    grid per pass over the replay time, against 8 TB/s."""
     import torch
     from paper_2103_08825_amd import Plan, workloads as W
     from paper_2103_08825_amd.batched import Batch
@@ -175,27 +177,84 @@ def bench_batched(a):
     t0 = time.time()
     batch = Batch(fused, xs, ys, Ts)
     log("batch build %.1fs, items/workgroups %s" % (time.time() - t0, batch.info()))
-    ms_batch = timed(batch.launch, max(3, a.steps))
+    ms_batch = timed(batch.launch, max(3, steps))
     batch.status()
-    ms_fused = ms_plain = float("nan")
-    if not a.no_compare:
+    # algorithmic bytes: every pass of a grid reads and writes it once (depth 8)
+    alg = float(sum(2 * 4 * x.numel() * (-(-T // 8)) for x, T in zip(xs, Ts)))
+    rec = {"value": work / (ms_batch * 1e-3) / 1e9, "unit": "GStencil/s", "ms": ms_batch,
+           "hbm_frac_alg": alg / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "points": int(sum(x.numel() for x in xs)), "point_steps": int(work),
+           "items": batch.info()[0], "workgroups": batch.info()[1]}
+    log("batched: %.3f ms per replay, %.1f GStencil/s" % (ms_batch, rec["value"]))
+    if compare:
         ms_fused = timed(lambda: [p.run(x, T, out=y) for p, x, y, T in zip(fused, xs, ys, Ts)], 2)
         plain = [Plan(g.shape, 1, g.kind, g.coeffs, W.BC_ZERO, "f32", method="plain") for g in grids]
         ms_plain = timed(lambda: [p.run(x, T, out=y) for p, x, y, T in zip(plain, xs, ys, Ts)], 2)
-    rec = {"metric": "GStencil/s, batched uneven 2D workload", "unit": "GStencil/s",
-           "value": work / (ms_batch * 1e-3) / 1e9, "ms_per_step": ms_batch, "n_gpus": 1,
-           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "256 2D grids, sides log-uniform [64,2048], 5P star or 9P box, "
-                                  "T in [10,200], zero halo", "points": int(sum(x.numel() for x in xs)),
-                      "point_steps": int(work), "items": batch.info()[0],
-                      "workgroups": batch.info()[1]},
-           "separate_plain": {"ms": ms_plain, "value": work / (ms_plain * 1e-3) / 1e9,
-                              "launches": int(sum(Ts))},
-           "separate_fused": {"ms": ms_fused, "value": work / (ms_fused * 1e-3) / 1e9},
-           "speedup_vs_plain": ms_plain / ms_batch, "speedup_vs_separate_fused": ms_fused / ms_batch}
-    print(json.dumps(rec), flush=True)
+        rec["separate_plain"] = {"ms": ms_plain, "value": work / (ms_plain * 1e-3) / 1e9, "launches": int(sum(Ts))}
+        rec["separate_fused"] = {"ms": ms_fused, "value": work / (ms_fused * 1e-3) / 1e9}
+        rec["speedup_vs_plain"] = ms_plain / ms_batch
+        rec["speedup_vs_separate_fused"] = ms_fused / ms_batch
+        for p in plain:
+            p.close()
     batch.close()
+    for p in fused:
+        p.close()
+    return rec
+
+
+def bench_batched(a):
+    """The batched 256-grid workload as one JSON line."""
+    r = batched_rate(a.steps, not a.no_compare)
+    rec = {"metric": "GStencil/s, batched uneven 2D workload", "unit": "GStencil/s",
+           "value": r["value"], "ms_per_step": r["ms"], "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": "256 2D grids, sides log-uniform [64,2048], 5P star or 9P box, "
+                                  "T in [10,200], zero halo", "points": r["points"],
+                      "point_steps": r["point_steps"], "items": r["items"], "workgroups": r["workgroups"]},
+           "batched": r}
+    print(json.dumps(rec), flush=True)
     return 0
+
+
+def other_configs():
+    """The other workloads of the hot path at the library's defaults, for the
+    headline line: 2D 5P/9P 8192^2 FP32 periodic (T=100), the batched 256-grid
+    workload, the adjoint of the 3D 7P 256^3 FP32 periodic sweep (T=100,
+    checkpoints every 10) and the 1D 3P 262,144-point FP64 sweep (T=200)."""
+    import torch
+    from paper_2103_08825_amd import Plan, workloads as W
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+
+    def sweep(case, dt):
+        tdt = {"f64": torch.float64, "f32": torch.float32}[dt]
+        x = torch.from_numpy(case.u0).to(tdt).cuda()
+        y = torch.empty_like(x)
+        plan = Plan(case.shape, case.r, case.kind, case.coeffs, case.bc, dt)
+        plan.run(x, case.T, out=y)
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(3):
+            e0.record()
+            plan.run(x, case.T, out=y)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        info = plan.info()
+        k = info["fused_k"]
+        pts = float(np.prod(case.shape))
+        plan.close()
+        return {"value": pts * case.T / best / 1e6, "unit": "GStencil/s", "ms": best, "k": k,
+                "variant": info["variant"], "hbm_frac_alg": 2.0 * x.element_size() * pts * (-(-case.T // k))
+                / (best * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    for kind, nm in ((W.STAR, "2d5p_8192_f32_periodic"), (W.BOX, "2d9p_8192_f32_periodic")):
+        out[nm] = sweep(W.case_2d(kind), "f32")
+        log("%s: %.1f GStencil/s (k=%d)" % (nm, out[nm]["value"], out[nm]["k"]))
+    out["1d3p_262144_f64"] = sweep(W.case_1d3p(), "f64")
+    out["batched_256_2d_f32"] = batched_rate(3, False)
+    out["adjoint_3d7p_256_f32_periodic"] = adjoint_rates(2)
+    return out
 
 
 def bench_table1(a):
@@ -404,6 +463,8 @@ def main(argv=None):
                          "tessellated one")
     ap.add_argument("--inplace", action="store_true",
                     help="headline sweep: update the field in place (no ping-pong field)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="headline line without the other workloads' sub-record")
     ap.add_argument("--no-compare", action="store_true",
                     help="batched: time the batch only, not the 256 separate sweeps")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -531,6 +592,13 @@ def main(argv=None):
         p64.close()
         del x64, y64
 
+    configs = None
+    if not a.no_configs and a.method == "fused" and not a.inplace:
+        # free the headline fields before the other workloads allocate theirs
+        del y
+        configs = other_configs()
+        y = None
+
     cpu = None
     if not a.no_cpu_baseline:
         log("cpu baseline ...")
@@ -552,6 +620,7 @@ def main(argv=None):
         "speedup_vs_plain": (plain_rec["ms_per_step"] / ms) if plain_rec else None,
         "roofline": roof, "roofline_alu": roof_alu, "cpu_baseline": cpu,
         "fp64": f64_rec,
+        "other_configs": configs,
     }
     print(json.dumps(rec), flush=True)
     fused.close()

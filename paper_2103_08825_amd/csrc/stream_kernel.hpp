@@ -254,14 +254,17 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<typename ComputeOf<
         }
     }
 
-    // Star stencils take the zero halo through their weights: a term whose
+    // 3D star stencils take the zero halo through their weights: a term whose
     // neighbour lies outside the grid gets weight 0, so points outside the grid
     // may hold any finite value (they start at 0 and only ever receive weighted
     // sums of finite values) and no level needs masking.  The x test is per lane
     // and lane shift (a lane's VX columns are all inside or all outside), the y
     // test per row (uniform per wave), the z test per source plane (uniform per
-    // step).  Box stencils mix axes in one term and keep the per-level masks.
-    constexpr bool kWeightHalo = !BOX;
+    // step).  Box stencils mix axes in one term and keep the per-level masks;
+    // so do 2D grids, whose waves hold one row: there the per-level scalar work
+    // of the z test outweighs the row's few FMAs, while interior tiles of the
+    // masked scheme need no mask at all.
+    constexpr bool kWeightHalo = !BOX && DIM == 3;
     constexpr int SHX = (R + VX - 1) / VX;  // lane shifts an x neighbour can need
     const int pmask = -a.bc;                  // -1 periodic, 0 zero halo
     int xnb[2 * SHX + 1];                     // per lane: the neighbour lane is inside
