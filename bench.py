@@ -458,6 +458,8 @@ def main(argv=None):
                          "in one graph-captured persistent launch vs separate sweeps; table1: "
                          "the paper's six evaluation problems in FP64; configs: every "
                          "workload, fused and plain, and the adjoint; adjoint: the adjoint alone")
+    ap.add_argument("--stencil", choices=["3d7p", "3d13p", "3d27p"], default="3d7p",
+                    help="headline sweep's stencil (default: the 3D 7-point star)")
     ap.add_argument("--method", choices=["fused", "tessellate"], default="fused",
                     help="headline sweep: the overlapped fused sweep (default) or the "
                          "tessellated one")
@@ -508,7 +510,8 @@ def main(argv=None):
         return bench_configs(a)
     if a.workload == "adjoint":
         return bench_adjoint(a)
-    case = W.case_3d("3d7p", seed=0, n=n, T=T)
+    case = W.case_3d(a.stencil, seed=0, n=n, T=T)
+    sname = {"3d7p": "3D 7-point star r=1", "3d13p": "3D 13-point star r=2", "3d27p": "3D 27-point box r=1"}[a.stencil]
     log("inputs: %s %s T=%d" % (case.name, case.shape, T))
     x = torch.from_numpy(case.u0).to(torch.float32).cuda()
     y = torch.empty_like(x)
@@ -556,13 +559,13 @@ def main(argv=None):
     if os.path.exists(PROFILE_TRAFFIC):
         with open(PROFILE_TRAFFIC) as f:
             prof = json.load(f)
-        if (prof.get("source_hash") == kernel_source_hash() and prof.get("k") == k and
+        if (a.stencil == "3d7p" and prof.get("source_hash") == kernel_source_hash() and prof.get("k") == k and
                 prof.get("variant") == info["variant"] and prof.get("chunk") == info["tile"][2]):
             traffic = prof.get("bytes_per_launch")
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "stream_kernel<float,3,R=1,star,K=%d> variant %d%s" % (
-                k, info["variant"], {"fused": "", "tessellate": ", tessellated (stages A and B per pass)"}[a.method]
+            "kernel": "stream_kernel<float,3,R=%d,%s,K=%d> variant %d%s" % (
+                case.r, "box" if case.kind else "star", k, info["variant"], {"fused": "", "tessellate": ", tessellated (stages A and B per pass)"}[a.method]
                 + (", in place (plus the fix-up kernel)" if a.inplace else "")),
             "launch_ms": launch_ms, "launch_ms_from_sweep": ms_sweep * k / T,
             "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs}
@@ -593,7 +596,7 @@ def main(argv=None):
         del x64, y64
 
     configs = None
-    if not a.no_configs and a.method == "fused" and not a.inplace:
+    if not a.no_configs and a.method == "fused" and not a.inplace and a.stencil == "3d7p":
         # free the headline fields before the other workloads allocate theirs
         del y
         configs = other_configs()
@@ -612,7 +615,7 @@ def main(argv=None):
         "metric": METRIC, "value": gst, "unit": "GStencil/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "3D 7-point star r=1, %d^3 grid, FP32, zero halo, T=%d" % (n, T),
+        "config": {"workload": "%s, %d^3 grid, FP32, zero halo, T=%d" % (sname, n, T),
                    "fused_k": k, "variant": info["variant"], "tile": info["tile"],
                    "points": int(points), "T": T},
         "sweep_ms_per_step": ms_sweep, "wall_ms_per_step": wall,
