@@ -240,8 +240,11 @@ int stencil_batch_set_wait_limit(stencil_batch *b, int64_t limit_us, void *strea
  * overwritten).  The adjoint step is the mirrored stencil (weight c_j at
  * offset -o_j, same boundary rule); dL/dc_j sums lambda_{t+1}[x]*u_t[x+o_j]
  * over x and t with FP64 partials.  Forward states are checkpointed every
- * checkpoint_every steps and recomputed per segment (device memory:
- * about (ceil(T/ckpt) + ckpt + 2) fields).  F64 and F32 plans only
+ * checkpoint_every steps and recomputed per segment (device memory: about
+ * (ceil(T/ckpt) + ckpt + 2) fields, or + 2 ckpt where the fused adjoint pass
+ * applies: it rebuilds the next segment on a second stream owned by the plan
+ * while the current one runs, and `stream` waits for that stream before the
+ * call's work ends).  One call at a time per plan.  F64 and F32 plans only
  * (STENCIL_E_UNSUPPORTED otherwise). */
 int stencil_adjoint(stencil_plan *p, const void *d_u0, const void *d_gT, int64_t T,
                     int64_t checkpoint_every, void *d_grad_u0, double *d_grad_coeffs,

@@ -507,6 +507,34 @@ static bool fused_adjoint_choice(const stencil_plan *p, FusedAdjoint *out) {
 
 constexpr int kMaxLevelsK = 8;  // deepest level-storing pass the recompute uses
 
+// The plan's second stream and its events for the adjoint's overlapped
+// recompute, created on first use on the current device (default priority).
+static int aux_stream_ready(stencil_plan *p) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return STENCIL_E_DEVICE;
+    if (p->aux_stream && p->aux_device == dev) return STENCIL_OK;
+    for (hipEvent_t &e : p->aux_ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    if (p->aux_stream) (void)hipStreamDestroy(p->aux_stream);
+    p->aux_stream = nullptr;
+    bool ok = hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t &e : p->aux_ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        for (hipEvent_t &e : p->aux_ev) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+        if (p->aux_stream) (void)hipStreamDestroy(p->aux_stream);
+        p->aux_stream = nullptr;
+        (void)hipGetLastError();  // the sequential path runs instead; keep no error behind
+        return STENCIL_E_DEVICE;
+    }
+    p->aux_device = dev;
+    return STENCIL_OK;
+}
+
 // The level-storing forward pass for a segment's recompute, where one is
 // compiled: (variant, deepest k) and, per depth, the chunk balanced over the
 // workgroups the device holds at once; k = 0 when none.
@@ -560,19 +588,36 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
     const size_t fstride = (field + 255) & ~(size_t)255;
     FusedAdjoint fa{0, 0, 0, 0};
     const bool fused = fused_adjoint_choice(p, &fa);
+    // The fused path rebuilds segment s-1 on a second stream while the mirrored
+    // steps of segment s run: two segment buffers, used alternately.
+    const bool overlap = fused && nseg > 1 && nst > 0 && aux_stream_ready(p) == STENCIL_OK;
+    const int64_t nbuf = overlap ? 2 : 1;
     const int64_t prow = fused ? fa.rows : kGradBlocks;  // partial rows of npts doubles
     const size_t part_bytes = (size_t)prow * p->npts * sizeof(double);
     const size_t tab_bytes = off3m.size() * sizeof(int);
-    const size_t ws_bytes = (size_t)(nck + nst + 2) * fstride + part_bytes + tab_bytes;
+    const size_t ws_bytes = (size_t)(nck + nbuf * nst + 2) * fstride + part_bytes + tab_bytes;
     char *ws = nullptr;
     STN_HIP(hipMallocAsync((void **)&ws, ws_bytes, st));
     auto ck = [&](int64_t s) -> void * { return s == 0 ? const_cast<void *>(d_u0) : ws + (size_t)(s - 1) * fstride; };
-    char *seg_base = ws + (size_t)nck * fstride;
-    char *lam_buf[2] = {ws + (size_t)(nck + nst) * fstride, ws + (size_t)(nck + nst + 1) * fstride};
-    double *part = reinterpret_cast<double *>(ws + (size_t)(nck + nst + 2) * fstride);
+    char *seg_buf[2] = {ws + (size_t)nck * fstride, ws + (size_t)(nck + (nbuf - 1) * nst) * fstride};
+    char *lam_buf[2] = {ws + (size_t)(nck + nbuf * nst) * fstride, ws + (size_t)(nck + nbuf * nst + 1) * fstride};
+    double *part = reinterpret_cast<double *>(ws + (size_t)(nck + nbuf * nst + 2) * fstride);
     int *d_offm = reinterpret_cast<int *>(reinterpret_cast<char *>(part) + part_bytes);
+    hipStream_t st2 = overlap ? p->aux_stream : st;
+    hipEvent_t ev_fwd = overlap ? p->aux_ev[0] : nullptr, ev_rec = overlap ? p->aux_ev[1] : nullptr;
+    hipEvent_t ev_adj = overlap ? p->aux_ev[2] : nullptr, ev_tail = overlap ? p->aux_ev[3] : nullptr;
+#define STN_HIP_DONE(expr)                                                                          \
+    do {                                                                                            \
+        const hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return done(fail(STENCIL_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
     int rc = STENCIL_OK;
     auto done = [&](int code) {
+        if (overlap) {
+            // nothing on the second stream may outlive the workspace
+            (void)hipEventRecord(ev_tail, st2);
+            (void)hipStreamWaitEvent(st, ev_tail, 0);
+        }
         (void)hipFreeAsync(ws, st);
         return code;
     };
@@ -584,31 +629,62 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
     for (int64_t s = 1; s < nseg && rc == STENCIL_OK; ++s) rc = run_passes(p, ex, ck(s - 1), ck(s), C, st);
     if (rc != STENCIL_OK) return done(rc);
 
+    int lvar = 0, lk = 0, lchunk[kMaxLevelsK + 1];
+    levels_choice(p, &lvar, &lk, lchunk);
+    // forward state t of segment s (t in [tb, te)): the checkpoint, else the
+    // segment buffer the segment was rebuilt into
+    auto seg_state = [&](int64_t s, int64_t t) -> const void * {
+        const int64_t tb = s * C;
+        return t == tb ? ck(s) : static_cast<const void *>(seg_buf[s & 1] + (size_t)(t - tb - 1) * fstride);
+    };
+    // rebuild states tb+1 .. te-1 of segment s on stream `sq`
+    auto recompute = [&](int64_t s, hipStream_t sq) -> int {
+        const int64_t tb = s * C, te = (tb + C < T) ? tb + C : T;
+        for (int64_t t = tb + 1; t < te;) {
+            const int kk = (int)std::min<int64_t>(lk, te - t);
+            if (kk >= 2) {
+                // states t .. t+kk-1 in one launch: level j to state(t-1+j)
+                SweepLaunch L{seg_state(s, t - 1), const_cast<void *>(seg_state(s, t + kk - 1)), p->n0, p->n1, p->n2,
+                              p->bc, p->dense.data(), lchunk[kk], nullptr, {}, nullptr};
+                for (int j = 1; j < kk; ++j) L.ustate[j - 1] = seg_state(s, t - 1 + j);
+                const SweepLauncher fn =
+                    find_launcher(KernelKey{p->dtype, p->dim, p->r, p->kind == STENCIL_BOX ? 1 : 0, lvar, kk, 4});
+                if (!fn) return fail(STENCIL_E_UNSUPPORTED, "no level-storing kernel with k=%d", kk);
+                const hipError_t le = fn(L, sq);
+                if (le != hipSuccess) return fail(STENCIL_E_DEVICE, "recompute launch: %s", hipGetErrorString(le));
+                t += kk;
+            } else {
+                const int r1 = one_step(p, ex1, p->dense, p->d_off, p->d_coef, seg_state(s, t - 1),
+                                        const_cast<void *>(seg_state(s, t)), sq);
+                if (r1 != STENCIL_OK) return r1;
+                ++t;
+            }
+        }
+        return STENCIL_OK;
+    };
+    if (overlap) STN_HIP_DONE(hipEventRecord(ev_fwd, st));
+
     const void *lam = d_gT;
     int flip = 0;
     for (int64_t s = nseg - 1; s >= 0; --s) {
         const int64_t tb = s * C, te = (tb + C < T) ? tb + C : T;
-        auto state = [&](int64_t t) -> const void * {
-            return t == tb ? ck(s) : static_cast<const void *>(seg_base + (size_t)(t - tb - 1) * fstride);
-        };
-        int lvar = 0, lk = 0, lchunk[kMaxLevelsK + 1];
-        levels_choice(p, &lvar, &lk, lchunk);
-        for (int64_t t = tb + 1; t < te && rc == STENCIL_OK;) {
-            const int kk = (int)std::min<int64_t>(lk, te - t);
-            if (kk >= 2) {
-                // states t .. t+kk-1 in one launch: level j to state(t-1+j)
-                SweepLaunch L{state(t - 1), const_cast<void *>(state(t + kk - 1)), p->n0, p->n1, p->n2, p->bc,
-                              p->dense.data(), lchunk[kk], nullptr, {}, nullptr};
-                for (int j = 1; j < kk; ++j) L.ustate[j - 1] = state(t - 1 + j);
-                const SweepLauncher fn =
-                    find_launcher(KernelKey{p->dtype, p->dim, p->r, p->kind == STENCIL_BOX ? 1 : 0, lvar, kk, 4});
-                if (!fn) return done(fail(STENCIL_E_UNSUPPORTED, "no level-storing kernel with k=%d", kk));
-                e = fn(L, st);
-                if (e != hipSuccess) return done(fail(STENCIL_E_DEVICE, "recompute launch: %s", hipGetErrorString(e)));
-                t += kk;
-            } else {
-                rc = one_step(p, ex1, p->dense, p->d_off, p->d_coef, state(t - 1), const_cast<void *>(state(t)), st);
-                ++t;
+        auto state = [&](int64_t t) -> const void * { return seg_state(s, t); };
+        if (!overlap) {
+            rc = recompute(s, st);
+        } else {
+            // segment s: rebuilt on this stream (the last one) or on the second
+            // stream during the previous iteration
+            if (s == nseg - 1)
+                rc = recompute(s, st);
+            else
+                STN_HIP_DONE(hipStreamWaitEvent(st, ev_rec, 0));
+            // segment s-1 on the second stream, into the buffer the mirrored steps
+            // of segment s+1 have finished reading (the first time: after the
+            // forward sweep wrote the checkpoints)
+            if (rc == STENCIL_OK && s >= 1) {
+                STN_HIP_DONE(hipStreamWaitEvent(st2, s == nseg - 1 ? ev_fwd : ev_adj, 0));
+                rc = recompute(s - 1, st2);
+                if (rc == STENCIL_OK) STN_HIP_DONE(hipEventRecord(ev_rec, st2));
             }
         }
         if (rc != STENCIL_OK) return done(rc);
@@ -628,6 +704,7 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
                 flip ^= 1;
                 t -= kk;
             }
+            if (overlap) STN_HIP_DONE(hipEventRecord(ev_adj, st));
             continue;
         }
         for (int64_t t = te - 1; t >= tb; --t) {
@@ -649,6 +726,7 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
     if (e != hipSuccess) return done(fail(STENCIL_E_DEVICE, "gradient fold: %s", hipGetErrorString(e)));
     return done(STENCIL_OK);
 }
+#undef STN_HIP_DONE
 
 }  // namespace stn
 

@@ -817,6 +817,9 @@ void stencil_plan_destroy(stencil_plan *p) {
     if (p->d_off) (void)hipFree(p->d_off);
     if (p->d_coef) (void)hipFree(p->d_coef);
     if (p->slope) (void)hipFree(p->slope);
+    for (hipEvent_t e : p->aux_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (p->aux_stream) (void)hipStreamDestroy(p->aux_stream);
     delete p;
 }
 

@@ -63,6 +63,11 @@ struct stencil_plan {
     void *graph_out;
     int64_t graph_T;
     int graph_failed;               // capture failed once: run with direct launches
+    // adjoint: a second stream for the segment recompute and its events
+    // (created on first use, on aux_device)
+    hipStream_t aux_stream;
+    hipEvent_t aux_ev[4];
+    int aux_device;
 };
 
 namespace stn {
