@@ -39,15 +39,10 @@ template <> __device__ __forceinline__ _Float16 from_compute<_Float16>(float v) 
     return (_Float16)v;  // v_cvt_f16_f32, round to nearest even
 }
 template <> __device__ __forceinline__ bf16_t from_compute<bf16_t>(float v) {
-    // round to nearest even on the upper 16 bits; NaN stays a quiet NaN
-    uint32_t u = __float_as_uint(v);
+    // round to nearest even (gfx950 converts in one instruction,
+    // v_cvt_pk_bf16_f32); a NaN stays a NaN
     bf16_t r;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-        r.bits = (uint16_t)((u >> 16) | 0x0040u);
-    } else {
-        u += 0x7fffu + ((u >> 16) & 1u);
-        r.bits = (uint16_t)(u >> 16);
-    }
+    r.bits = __builtin_bit_cast(uint16_t, (__bf16)v);
     return r;
 }
 
