@@ -310,7 +310,7 @@ def _unmasked_workgroups(shape, r, k, variant, tile):
     return count
 
 
-@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16", "f64"])
 @pytest.mark.parametrize("name", ["3d7p", "3d27p", "3d13p"])
 def test_default_tiles_on_interior_reaching_grid(name, dt):
     """The 512^3 defaults (tile variant and fused depth of every stencil and
