@@ -178,10 +178,10 @@ static const Choice kChoices[] = {
     {3, 1, STENCIL_STAR, 1, 5, 6, 0, 3, 8}, {3, 1, STENCIL_BOX, 1, 5, 3, 0, 5, 0},
     {3, 2, STENCIL_STAR, 1, 4, 2, 64, 5, 0},
     // 3D 16-bit storage
-    {3, 1, STENCIL_STAR, 2, 5, 6, 0, 5, 0}, {3, 1, STENCIL_BOX, 2, 4, 3, 64, 4, 0},
+    {3, 1, STENCIL_STAR, 2, 5, 6, 0, 5, 0}, {3, 1, STENCIL_BOX, 2, 5, 3, 0, 4, 0},
     {3, 2, STENCIL_STAR, 2, 4, 2, 64, 1, 64},
     // 3D FP64
-    {3, 1, STENCIL_STAR, 0, 4, 4, 0, 1, 32}, {3, 1, STENCIL_BOX, 0, 4, 2, 0, 1, 32},
+    {3, 1, STENCIL_STAR, 0, 4, 4, 0, 1, 32}, {3, 1, STENCIL_BOX, 0, 4, 3, 0, 1, 32},
     {3, 2, STENCIL_STAR, 0, 4, 2, 0, 4, 0},
     // 2D FP32: 5-point, 9-point
     {2, 1, STENCIL_STAR, 1, 2, 8, 0, 2, 64}, {2, 1, STENCIL_BOX, 1, 2, 8, 0, 2, 64},
