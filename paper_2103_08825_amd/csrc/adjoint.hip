@@ -477,9 +477,11 @@ static int one_step(stencil_plan *p, const Exec &ex, const std::vector<double> &
 // The fused adjoint pass (mirrored steps with the gradient folded in, kA
 // steps per launch) where one is compiled for the plan's stencil: the first
 // variant that has one, at its deepest compiled depth.
+constexpr int kMaxAdjointK = 8;
 struct FusedAdjoint {
-    int variant, k, chunk;
-    int64_t rows;  // gradient partial rows (the most any of its launches writes)
+    int variant, k;
+    int chunk[kMaxAdjointK + 1];  // per depth
+    int64_t rows;                 // gradient partial rows (the most any of its launches writes)
 };
 static bool fused_adjoint_choice(const stencil_plan *p, FusedAdjoint *out) {
     if (p->dim < 2 || (p->dtype != STENCIL_F32 && p->dtype != STENCIL_F64)) return false;
@@ -491,15 +493,17 @@ static bool fused_adjoint_choice(const stencil_plan *p, FusedAdjoint *out) {
         if (k < 1) continue;
         if (p->n1 * p->n2 * elem_bytes(p->dtype) >= ((int64_t)1 << 31) || p->n0 >= ((int64_t)1 << 31)) return false;
         if (vs.vx > 1 && p->n2 % vs.vx) continue;
-        // balanced over the workgroups the device holds at once (the pass holds
-        // about 200 registers per lane: one workgroup per compute unit)
-        const int chunk =
-            balanced_chunk(p->dim, p->r, k, vs, p->n0, p->n1, p->n2, resident_blocks(KernelKey{p->dtype, p->dim, p->r, box, v, k, 3}));
-        int64_t rows = 0;
-        for (int kk = 1; kk <= k; ++kk)
-            rows = std::max(rows, adjoint_part_rows(p->dim, p->r, kk, vs, p->n0, p->n1, p->n2, chunk));
-        if (rows <= 0) return false;
-        *out = FusedAdjoint{v, k, chunk, rows};
+        // per depth, chunks balanced over the workgroups the device holds at
+        // once (the deepest pass holds about 200 registers per lane: one
+        // workgroup per compute unit; shallower ones may fit more)
+        FusedAdjoint fa{v, std::min(k, kMaxAdjointK), {}, 0};
+        for (int kk = 1; kk <= fa.k; ++kk) {
+            fa.chunk[kk] = balanced_chunk(p->dim, p->r, kk, vs, p->n0, p->n1, p->n2,
+                                          resident_blocks(KernelKey{p->dtype, p->dim, p->r, box, v, kk, 3}));
+            fa.rows = std::max(fa.rows, adjoint_part_rows(p->dim, p->r, kk, vs, p->n0, p->n1, p->n2, fa.chunk[kk]));
+        }
+        if (fa.rows <= 0) return false;
+        *out = fa;
         return true;
     }
     return false;
@@ -586,7 +590,7 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
     // the caller's pointers assumes workspace fields at least as aligned)
     const int64_t nck = nseg - 1, nst = seglen - 1;
     const size_t fstride = (field + 255) & ~(size_t)255;
-    FusedAdjoint fa{0, 0, 0, 0};
+    FusedAdjoint fa{0, 0, {}, 0};
     const bool fused = fused_adjoint_choice(p, &fa);
     // The fused path rebuilds segment s-1 on a second stream while the mirrored
     // steps of segment s run: two segment buffers, used alternately.
@@ -693,7 +697,7 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
             for (int64_t t = te - 1; t >= tb;) {
                 const int kk = (int)std::min<int64_t>(fa.k, t - tb + 1);
                 void *out = (t + 1 - kk == 0) ? d_gu : lam_buf[flip];
-                SweepLaunch L{lam, out, p->n0, p->n1, p->n2, p->bc, dense_m.data(), fa.chunk, nullptr, {}, part};
+                SweepLaunch L{lam, out, p->n0, p->n1, p->n2, p->bc, dense_m.data(), fa.chunk[kk], nullptr, {}, part};
                 for (int j = 1; j <= kk; ++j) L.ustate[j - 1] = state(t + 1 - j);
                 const SweepLauncher fn =
                     find_launcher(KernelKey{p->dtype, p->dim, p->r, p->kind == STENCIL_BOX ? 1 : 0, fa.variant, kk, 3});
