@@ -315,6 +315,14 @@ static int resolve_exec(stencil_plan *p) {
         } else {
             k = default_k(p, variant);
             if (mc && variant == mc->variant && mc->k <= max_k_of(p, variant)) k = mc->k;
+            // The measured depths were chosen on 512^3 grids.  On a quarter of
+            // that or less the balanced chunks get short, and the fill of a deep
+            // pass (k(2r+1) planes per chunk) outweighs the saved passes: the 3D
+            // order-1 star stencils stop at k = 4 there (measured at 256^3 FP32,
+            // T = 10 per call: k = 6 1149, k = 5 1254, k = 4 1295 GStencil/s).
+            if (p->dim == 3 && p->r == 1 && p->kind == STENCIL_STAR && p->dtype != STENCIL_F64 &&
+                p->points <= kPlainSmallGrid / 2 && k > 4)
+                k = 4;
         }
     }
     ex.method = method;
