@@ -7,10 +7,18 @@ One timed step = one whole sweep (stencil_run, T = 64, with the library's
 measured default fused depth k, tile variant and z-chunk, or the autotuned
 ones with --autotune) followed by the FP64 checksum reduction of u_T, inputs
 resident in HBM.  The plain one-step-per-launch sweep (k = 1) is
-timed the same way for the speedup.
+timed the same way for the speedup.  The line also carries the roofline of
+the dominant kernel (HIP-event launch timing; counted HBM traffic while the
+kernel sources match the recorded profile), the same grid in FP64, the
+other workloads at their defaults (other_configs: 2D 8192^2 periodic, the
+batched 256-grid workload, the 256^3 adjoint, 1D FP64) and the FP64 CPU
+oracle timed on a bounded sample (cpu_baseline).
 
 Prints one JSON line.  Usage:
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                  [--no-configs] [--no-f64] [--stencil 3d7p|3d13p|3d27p]
+                  [--method fused|tessellate] [--inplace]
+  python bench.py --workload batched|table1|configs|adjoint
 """
 from __future__ import annotations
 
