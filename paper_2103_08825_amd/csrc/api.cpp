@@ -156,9 +156,13 @@ static int default_variant(const stencil_plan *p, int need_k) {
     return best;
 }
 
+// 1D: a halo of k*r = 32 points per side of a 256-point (4 per lane) segment
+// (measured, FP64 3-point: 262,144 points T = 200, k = 16 993 -> k = 32 1429
+// GStencil/s, launch-bound; 10,240,000 points T = 1000, 4506 -> 4757, k = 24
+// 4892; 5-point, k = 8 2671 -> k = 16 2896).
 static int default_k(const stencil_plan *p, int variant) {
     const int kmax = max_k_of(p, variant);
-    const int want = p->dim == 3 ? 4 : (p->dim == 2 ? 8 : 16);
+    const int want = p->dim == 3 ? 4 : (p->dim == 2 ? 8 : 32 / p->r);
     return std::min(want, kmax);
 }
 
@@ -317,12 +321,17 @@ static int resolve_exec(stencil_plan *p) {
             if (mc && variant == mc->variant && mc->k <= max_k_of(p, variant)) k = mc->k;
             // The measured depths were chosen on 512^3 grids.  On a quarter of
             // that or less the balanced chunks get short, and the fill of a deep
-            // pass (k(2r+1) planes per chunk) outweighs the saved passes: the 3D
-            // order-1 star stencils stop at k = 4 there (measured at 256^3 FP32,
-            // T = 10 per call: k = 6 1149, k = 5 1254, k = 4 1295 GStencil/s).
-            if (p->dim == 3 && p->r == 1 && p->kind == STENCIL_STAR && p->dtype != STENCIL_F64 &&
-                p->points <= kPlainSmallGrid / 2 && k > 4)
-                k = 4;
+            // pass (k(2r+1) planes per chunk) outweighs the saved passes, so the
+            // order-1 stencils stop earlier there: FP32 and 16-bit stars at k = 4
+            // (256^3 FP32, T = 10 per call: k = 6 1149, k = 5 1254, k = 4 1295
+            // GStencil/s), FP64 stars at k = 3 and FP64 boxes at k = 2 (128^3,
+            // T = 1000: 7-point 227 at k = 4, 242 at k = 3; 27-point 120 at
+            // k = 3, 156 at k = 2).
+            if (p->dim == 3 && p->r == 1 && p->points <= kPlainSmallGrid / 2) {
+                const int cap = p->dtype != STENCIL_F64 ? (p->kind == STENCIL_STAR ? 4 : k)
+                                                        : (p->kind == STENCIL_STAR ? 3 : 2);
+                if (k > cap) k = cap;
+            }
         }
     }
     ex.method = method;

@@ -29,7 +29,7 @@ FAMILIES = [
     (3, 1, 0, "f64", 2), (3, 1, 1, "f64", 2), (3, 2, 0, "f64", 2),
     (2, 1, 0, "f32", 8), (2, 1, 1, "f32", 8), (2, 2, 0, "f32", 4), (2, 2, 1, "f32", 4),
     (2, 1, 0, "f64", 4), (2, 1, 1, "f64", 4), (2, 2, 0, "f64", 2),
-    (1, 1, 0, "f64", 16), (1, 2, 0, "f64", 8), (1, 1, 0, "f32", 16), (1, 2, 0, "f32", 8),
+    (1, 1, 0, "f64", 32), (1, 2, 0, "f64", 16), (1, 1, 0, "f32", 32), (1, 2, 0, "f32", 16),
 ]
 
 
