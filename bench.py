@@ -187,8 +187,9 @@ def batched_rate(steps, compare):
     log("batch build %.1fs, items/workgroups %s" % (time.time() - t0, batch.info()))
     ms_batch = timed(batch.launch, max(3, steps))
     batch.status()
-    # algorithmic bytes: every pass of a grid reads and writes it once (depth 8)
-    alg = float(sum(2 * 4 * x.numel() * (-(-T // 8)) for x, T in zip(xs, Ts)))
+    # algorithmic bytes: every pass of a grid reads and writes it once (the
+    # batch's default depth for order-1 grids is 12 steps per pass)
+    alg = float(sum(2 * 4 * x.numel() * (-(-T // 12)) for x, T in zip(xs, Ts)))
     rec = {"value": work / (ms_batch * 1e-3) / 1e9, "unit": "GStencil/s", "ms": ms_batch,
            "hbm_frac_alg": alg / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "points": int(sum(x.numel() for x in xs)), "point_steps": int(work),

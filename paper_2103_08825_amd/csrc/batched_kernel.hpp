@@ -8,7 +8,11 @@ namespace stn {
 // the persistent kernel's tile shape: one column per lane (any width), 4 waves
 constexpr int kBatchVX = 1;
 constexpr int kBatchNW = 4;
-constexpr int kBatchMaxK1 = 8;  // fused steps compiled for order-1 stencils
+// fused steps compiled for order-1 stencils: deeper items mean fewer passes and
+// fewer dependency waits, which outweighs their wider recomputed halo up to 12
+// (uneven 256-grid workload, 128-row items: k = 6 1004, 8 1232, 12 1376,
+// 16 1181 GStencil/s; at 16 the kernel's registers leave fewer waves per CU)
+constexpr int kBatchMaxK1 = 12;
 constexpr int kBatchMaxK2 = 4;  // ... for order-2 stencils
 // rows per work item: large enough that an item's fill (k(2r+1) extra steps) and
 // bookkeeping are small, small enough that a grid's pass splits into many items
