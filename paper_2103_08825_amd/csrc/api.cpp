@@ -171,7 +171,9 @@ static int default_k(const stencil_plan *p, int variant) {
 // over the resident workgroups for the plan's shape).  stencil_autotune
 // refines them for a given plan.  The 3D 7-point FP32 depth is k = 6 since the
 // zero halo goes through the weights (sustained T = 64 sweeps, alternating
-// choices on one GPU: k = 6 2168, k = 5 2103, k = 4 1780 GStencil/s).
+// choices on one GPU: k = 6 2168, k = 5 2103, k = 4 1780 GStencil/s); the 2D
+// 5-point depth is k = 10 (8192^2 periodic, T = 100: k = 8 3583, k = 10 4128,
+// k = 12 4065), the 9-point stays at k = 8 (k = 10 the same, 12 slower).
 struct Choice {
     int dim, r, kind, dclass;  // dclass: 0 FP64, 1 FP32, 2 16-bit
     int variant, k, chunk;     // fused
@@ -188,7 +190,7 @@ static const Choice kChoices[] = {
     {3, 1, STENCIL_STAR, 0, 4, 4, 0, 1, 32}, {3, 1, STENCIL_BOX, 0, 4, 3, 0, 1, 32},
     {3, 2, STENCIL_STAR, 0, 4, 2, 0, 4, 0},
     // 2D FP32: 5-point, 9-point
-    {2, 1, STENCIL_STAR, 1, 2, 8, 0, 2, 64}, {2, 1, STENCIL_BOX, 1, 2, 8, 0, 2, 64},
+    {2, 1, STENCIL_STAR, 1, 2, 10, 0, 2, 64}, {2, 1, STENCIL_BOX, 1, 2, 8, 0, 2, 64},
 };
 
 static const Choice *measured_choice(const stencil_plan *p) {
@@ -338,6 +340,12 @@ static int resolve_exec(stencil_plan *p) {
     ex.variant = variant;
     ex.k = k;
     ex.chunk = chunk > 0 ? chunk : auto_chunk(p, variant, k);
+    // a default depth beyond what the in-place pass compiles drops to its deepest
+    if (o.inplace && o.fused_k == 0 && method == STENCIL_METHOD_FUSED && inplace_max_k(p, ex.variant) > 0 &&
+        inplace_max_k(p, ex.variant) < ex.k) {
+        ex.k = inplace_max_k(p, ex.variant);
+        ex.chunk = chunk > 0 ? chunk : auto_chunk(p, ex.variant, ex.k);
+    }
     if (o.inplace && inplace_max_k(p, ex.variant) < ex.k) {
         // the in-place pass is compiled for fewer variants: the widest that is
         int alt = 0;

@@ -67,6 +67,13 @@ def test_fused_matches_oracle(fam, bc):
         _check(dim, r, kind, bc, dt, shape, "fused", k, Ts, seed=k)
 
 
+@pytest.mark.parametrize("bc", [0, 1])
+def test_2d_star_deepest_wide_lanes(bc):
+    """The 2D 5-point star's deepest pass on 4-column lanes (the 8192^2 default
+    depth), with remainders, against the oracle."""
+    _check(2, 1, 0, bc, "f32", SHAPES_VX[2], "fused", 10, [3, 10, 11, 21], variant=2, seed=31)
+
+
 @pytest.mark.parametrize("dim", [1, 2, 3])
 @pytest.mark.parametrize("bc", [0, 1])
 def test_wide_lane_variants(dim, bc):
