@@ -200,7 +200,7 @@ int stencil_run_batched(stencil_plan *const *plans, int n, const void *const *d_
  * buffers must outlive the batch.  Each replay recomputes the outputs from the
  * inputs.  Per grid, a pass runs the plan's requested fused depth (opts.fused_k),
  * one step for plans created with the plain or generic method, else the deepest
- * depth the batched kernel compiles (8 for r = 1, 4 for r = 2), or the tuned
+ * depth the batched kernel compiles (12 for r = 1, 4 for r = 2), or the tuned
  * depth when flags bit 0 is set; a pass splits into work items of opts.chunk
  * rows (default 128).  flags: bit 0 = autotune each distinct plan first and
  * take its tuned depth. */
