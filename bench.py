@@ -155,7 +155,9 @@ def launch_probe(plan, buf, k, n):
 def batched_rate(steps, compare):
     """256 independent 2D FP32 grids (sides log-uniform in [64, 2048], 5-point star
     or 9-point box, T uniform in [10, 200], zero halo): one graph-captured
-    persistent launch (library default depth and chunk), optionally against 256
+    persistent launch whose item depth (per stencil) and rows per item the
+    library's item tuner chose by timing this batch's own replays (the untuned
+    defaults are timed beside it), optionally against 256
     separate plain sweeps (k = 1, one launch per step) and 256 separate fused
     sweeps.  Returns a record; hbm_frac_alg is one read and one write of every
     grid per pass over the replay time, against 8 TB/s."""
@@ -183,18 +185,32 @@ def batched_rate(steps, compare):
 
     fused = [Plan(g.shape, 1, g.kind, g.coeffs, W.BC_ZERO, "f32") for g in grids]
     t0 = time.time()
-    batch = Batch(fused, xs, ys, Ts)
-    log("batch build %.1fs, items/workgroups %s" % (time.time() - t0, batch.info()))
+    default = Batch(fused, xs, ys, Ts)
+    log("batch build %.1fs, items/workgroups %s" % (time.time() - t0, default.info()))
+    ms_default = timed(default.launch, max(3, steps))
+    default.status()
+    default_choice = default.choice()
+    default.close()
+    t0 = time.time()
+    batch = Batch(fused, xs, ys, Ts, tune_items=True)
+    tune_s = time.time() - t0
+    depths, rows = batch.choice()
+    log("item tuner %.2fs: depths (5P, 9P) %s, rows %d" % (tune_s, depths[:2], rows))
     ms_batch = timed(batch.launch, max(3, steps))
     batch.status()
-    # algorithmic bytes: every pass of a grid reads and writes it once (the
-    # batch's default depth for order-1 grids is 12 steps per pass)
-    alg = float(sum(2 * 4 * x.numel() * (-(-T // 12)) for x, T in zip(xs, Ts)))
+    # algorithmic bytes: every pass of a grid reads and writes it once (order-1
+    # grids: depths[0] steps per pass for the 5-point star, depths[1] for the box)
+    alg = float(sum(2 * 4 * x.numel() * (-(-T // depths[g.kind])) for x, T, g in zip(xs, Ts, grids)))
     rec = {"value": work / (ms_batch * 1e-3) / 1e9, "unit": "GStencil/s", "ms": ms_batch,
            "hbm_frac_alg": alg / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "points": int(sum(x.numel() for x in xs)), "point_steps": int(work),
-           "items": batch.info()[0], "workgroups": batch.info()[1]}
-    log("batched: %.3f ms per replay, %.1f GStencil/s" % (ms_batch, rec["value"]))
+           "items": batch.info()[0], "workgroups": batch.info()[1],
+           "tuned": {"depth_5p": depths[0], "depth_9p": depths[1], "rows": rows, "tune_s": tune_s},
+           "untuned": {"ms": ms_default, "value": work / (ms_default * 1e-3) / 1e9,
+                       "depth_5p": default_choice[0][0], "depth_9p": default_choice[0][1],
+                       "rows": default_choice[1]}}
+    log("batched: %.3f ms per replay, %.1f GStencil/s (untuned %.3f ms, %.1f)"
+        % (ms_batch, rec["value"], ms_default, rec["untuned"]["value"]))
     if compare:
         ms_fused = timed(lambda: [p.run(x, T, out=y) for p, x, y, T in zip(fused, xs, ys, Ts)], 2)
         plain = [Plan(g.shape, 1, g.kind, g.coeffs, W.BC_ZERO, "f32", method="plain") for g in grids]

@@ -203,10 +203,23 @@ int stencil_run_batched(stencil_plan *const *plans, int n, const void *const *d_
  * depth the batched kernel compiles (12 for r = 1, 4 for r = 2), or the tuned
  * depth when flags bit 0 is set; a pass splits into work items of opts.chunk
  * rows (default 128).  flags: bit 0 = autotune each distinct plan first and
- * take its tuned depth. */
+ * take its tuned depth; bit 1 = tune the items instead on this batch's own
+ * persistent kernel: a coordinate search over the depth of each stencil class
+ * present (order 1: 6, 8, 10, 12; order 2: 2, 3, 4) and then over the rows per
+ * item (64, 96, 128, 192, 256), timing whole replays, so creation runs the
+ * batch several times (reading d_in, overwriting d_out) on `stream`; a plan's
+ * requested fused_k, method or chunk still wins, and the choice is cached
+ * in-process per workload and device architecture.  Other bits:
+ * STENCIL_E_INVALID. */
 int stencil_batch_create(stencil_batch **out, stencil_plan *const *plans, int n,
                          const void *const *d_in, void *const *d_out, const int64_t *T,
                          int flags, void *stream);
+/* The item shape a batch runs (batched extension): depths[0..3] = fused steps
+ * per item for order-1 star, order-1 box, order-2 star, order-2 box grids
+ * whose plan requests no depth (0 for a class the batch does not hold), and
+ * *chunk = rows per item for grids whose plan requests no chunk.  Either
+ * pointer may be NULL.  STENCIL_E_INVALID for a NULL batch. */
+int stencil_batch_choice(const stencil_batch *b, int *depths, int *chunk);
 /* Replays the captured graph on `stream` (batched extension). */
 int stencil_batch_launch(stencil_batch *b, void *stream);
 /* Frees the batch (NULL-safe); the caller must have synchronised its stream

@@ -30,7 +30,7 @@ EXPORTS = (
     "stencil_num_points", "stencil_offsets", "stencil_plan_create", "stencil_plan_destroy",
     "stencil_plan_info", "stencil_plan_prepare", "stencil_autotune", "stencil_run",
     "stencil_run_batched", "stencil_batch_create", "stencil_batch_launch", "stencil_batch_destroy",
-    "stencil_batch_info", "stencil_batch_status", "stencil_batch_set_wait_limit", "stencil_adjoint", "stencil_reduce", "stencil_reduce_noalloc", "stencil_last_error",
+    "stencil_batch_info", "stencil_batch_choice", "stencil_batch_status", "stencil_batch_set_wait_limit", "stencil_adjoint", "stencil_reduce", "stencil_reduce_noalloc", "stencil_last_error",
     "stencil_version",
 )
 
@@ -86,6 +86,7 @@ def lib():
             "stencil_batch_launch": (ci, [vp, vp]),
             "stencil_batch_destroy": (None, [vp]),
             "stencil_batch_info": (ci, [vp, P(i64), P(i64)]),
+            "stencil_batch_choice": (ci, [vp, P(ci), P(ci)]),
             "stencil_batch_status": (ci, [vp, vp]),
             "stencil_batch_set_wait_limit": (ci, [vp, i64, vp]),
             "stencil_adjoint": (ci, [vp, vp, vp, i64, i64, vp, vp, vp]),
@@ -201,6 +202,13 @@ def stencil_batch_info(batch: int):
     items, wgs = ctypes.c_int64(), ctypes.c_int64()
     check(lib().stencil_batch_info(batch, ctypes.byref(items), ctypes.byref(wgs)), "stencil_batch_info")
     return items.value, wgs.value
+
+
+def stencil_batch_choice(batch: int):
+    """(depths for order-1 star, order-1 box, order-2 star, order-2 box; rows per item)"""
+    depths, chunk = (ctypes.c_int * 4)(), ctypes.c_int()
+    check(lib().stencil_batch_choice(batch, depths, ctypes.byref(chunk)), "stencil_batch_choice")
+    return list(depths), chunk.value
 
 
 def stencil_batch_status(batch: int, stream: int) -> None:

@@ -13,7 +13,11 @@ class Batch:
     """A captured batched sweep.  Plans and tensors must outlive it."""
 
     def __init__(self, plans: Sequence[Plan], inputs: Sequence[torch.Tensor],
-                 outputs: Sequence[torch.Tensor], Ts: Sequence[int], autotune: bool = False):
+                 outputs: Sequence[torch.Tensor], Ts: Sequence[int], autotune: bool = False,
+                 tune_items: bool = False):
+        """autotune: tune each plan on single-grid launches and take its depth;
+        tune_items: tune the items' depth and rows on this batch's persistent
+        kernel (creation replays the batch several times, overwriting outputs)."""
         if not (len(plans) == len(inputs) == len(outputs) == len(Ts)):
             raise ValueError("plans, inputs, outputs and Ts differ in length")
         for p, x, y in zip(plans, inputs, outputs):
@@ -23,7 +27,8 @@ class Batch:
         self.handle = _lib.stencil_batch_create([p.handle for p in plans],
                                                 [x.data_ptr() for x in inputs],
                                                 [y.data_ptr() for y in outputs], list(Ts),
-                                                1 if autotune else 0, _stream())
+                                                (1 if autotune else 0) | (2 if tune_items else 0),
+                                                _stream())
 
     def launch(self) -> None:
         _lib.stencil_batch_launch(self.handle, _stream())
@@ -38,6 +43,10 @@ class Batch:
 
     def info(self):
         return _lib.stencil_batch_info(self.handle)
+
+    def choice(self):
+        """([order-1 star, order-1 box, order-2 star, order-2 box] depths, rows per item)"""
+        return _lib.stencil_batch_choice(self.handle)
 
     def close(self) -> None:
         if getattr(self, "handle", None):

@@ -19,7 +19,9 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "batched_kernel.hpp"
@@ -29,6 +31,8 @@
 
 struct stencil_batch {
     int device;
+    int depth[2][2];  // item depth per stencil order (1, 2) and kind (star, box); 0: none chosen
+    int chunk;        // item rows chosen for grids without a requested chunk
     int dtype;
     int64_t nitems;
     int ngrids;
@@ -68,10 +72,17 @@ static int resident_workgroups(int dtype, int rmax, int *out) {
     return STENCIL_OK;
 }
 
-static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, const void *const *d_in,
-                       void *const *d_out, const int64_t *T, int flags, hipStream_t st) {
-    if (!out) return fail(STENCIL_E_INVALID, "out is NULL");
-    *out = nullptr;
+// The item shape of grids whose plan requests none: depth per stencil order and
+// kind (0: the deepest compiled, or the tuned single-grid depth under flags bit
+// 0) and rows per item (0: kBatchChunk).
+struct BatchChoice {
+    int depth[2][2];
+    int chunk;
+};
+
+// argument checks (host only, no device call)
+static int batch_validate(stencil_plan *const *plans, int n, const void *const *d_in, void *const *d_out,
+                          const int64_t *T) {
     if (!plans || n < 1 || !d_in || !d_out || !T) return fail(STENCIL_E_INVALID, "bad batch arguments");
     const int dtype = plans[0] ? plans[0]->dtype : -1;
     for (int i = 0; i < n; ++i) {
@@ -86,6 +97,17 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
         if (p->n0 >= ((int64_t)1 << 31) || p->n2 * elem_bytes(dtype) >= ((int64_t)1 << 31))
             return fail(STENCIL_E_UNSUPPORTED, "grid %d is too large for the batched kernel", i);
     }
+    return STENCIL_OK;
+}
+
+static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, const void *const *d_in,
+                       void *const *d_out, const int64_t *T, int flags, hipStream_t st,
+                       const BatchChoice &ch) {
+    if (!out) return fail(STENCIL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const int vrc = batch_validate(plans, n, d_in, d_out, T);
+    if (vrc != STENCIL_OK) return vrc;
+    const int dtype = plans[0]->dtype;
     if (flags & 1) {
         for (int i = 0; i < n; ++i) {
             const int rc = stencil_autotune(plans[i], st);
@@ -95,6 +117,7 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
     // per-grid geometry
     std::vector<BatchGrid> grids(n);
     int max_pass = 0;
+    int used[2][2] = {{0, 0}, {0, 0}};  // depth taken by grids without a requested one
     for (int i = 0; i < n; ++i) {
         const stencil_plan *p = plans[i];
         BatchGrid &g = grids[i];
@@ -108,9 +131,13 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
             k = 1;
         else if (p->opts.fused_k > 0)
             k = p->opts.fused_k;
+        else if (ch.depth[p->r - 1][p->kind == STENCIL_BOX ? 1 : 0] > 0)
+            k = ch.depth[p->r - 1][p->kind == STENCIL_BOX ? 1 : 0];
         else if (flags & 1)
             k = p->exec.k;
         k = std::max(1, std::min(k, kmax));
+        if (p->opts.method != STENCIL_METHOD_GENERIC && p->opts.method != STENCIL_METHOD_PLAIN && p->opts.fused_k <= 0)
+            used[p->r - 1][p->kind == STENCIL_BOX ? 1 : 0] = k;
         const int64_t Ti = T[i];
         g.k = k;
         g.krem = (int)(Ti % k);
@@ -124,7 +151,7 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
         g.bc = p->bc;
         // an explicitly requested chunk wins; a tuned or measured single-grid chunk
         // does not carry over (it is chosen to fill the GPU with one grid)
-        const int chunk = p->opts.chunk > 0 ? p->opts.chunk : kBatchChunk;
+        const int chunk = p->opts.chunk > 0 ? p->opts.chunk : (ch.chunk > 0 ? ch.chunk : kBatchChunk);
         const Geometry geo = stream_geometry(2, p->r, k, VariantShape{kBatchVX, kBatchNW, 1}, p->n0, 1, p->n2, chunk);
         if (!geo.ok) return fail(STENCIL_E_INVALID, "grid %d has no valid tiling", i);
         g.tiles_x = geo.tiles_x;
@@ -191,6 +218,8 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
     b->graph = nullptr;
     b->exec = nullptr;
     b->wait_ticks = kDefaultWaitTicks;
+    std::memcpy(b->depth, used, sizeof b->depth);
+    b->chunk = ch.chunk > 0 ? ch.chunk : kBatchChunk;
     auto cleanup = [&](int code) {
         if (b->exec) (void)hipGraphExecDestroy(b->exec);
         if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -259,6 +288,138 @@ static int batch_build(stencil_batch **out, stencil_plan *const *plans, int n, c
     return STENCIL_OK;
 }
 
+// Tuning the item shape on the persistent kernel itself.  The single-grid
+// tuner (flags bit 0) times launches that fill the GPU with one grid; a batch's
+// items share it with thousands of others, so their best depth and row count
+// differ.  Flags bit 1 instead times whole replays of the batch: a coordinate
+// search over the depth of each stencil class present (order 1: 6, 8, 10, 12;
+// order 2: 2, 3, 4), then over the rows per item (64 ... 256), starting from
+// the defaults and keeping a candidate only if its fastest replay beats the best
+// so far by more than 1%.  Candidates are built, replayed and freed in turn;
+// replays read d_in and overwrite d_out only.  The choice is cached in-process
+// per workload (dtype and every grid's shape, stencil, boundary, step count and
+// requested options) and device architecture.
+
+static int time_batch(stencil_batch *b, hipStream_t st, float *ms) {
+    *ms = 0.f;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = -1.f;
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, st);  // warm-up
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess) e = hipGraphLaunch(b->exec, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e == hipSuccess && (best < 0.f || t < best)) best = t;
+    }
+    int flag = 0;
+    if (e == hipSuccess) e = hipMemcpy(&flag, b->args.error, sizeof(int), hipMemcpyDeviceToHost);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(STENCIL_E_DEVICE, "batch tuning replay: %s", hipGetErrorString(e));
+    if (flag) return fail(STENCIL_E_DEVICE, "a batched work item waited past the spin limit while tuning");
+    *ms = best;
+    return STENCIL_OK;
+}
+
+static std::string batch_signature(stencil_plan *const *plans, int n, const int64_t *T) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string sig = "batch ";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        const std::string a = prop.gcnArchName;
+        sig += a.substr(0, a.find(':'));
+    }
+    char buf[160];
+    for (int i = 0; i < n; ++i) {
+        const stencil_plan *p = plans[i];
+        snprintf(buf, sizeof buf, "|%d %d %d %d %lld %lld %lld %d %d %d", p->dtype, p->r, p->kind, p->bc,
+                 (long long)p->n0, (long long)p->n2, (long long)T[i], p->opts.method, p->opts.fused_k,
+                 p->opts.chunk);
+        sig += buf;
+    }
+    return sig;
+}
+
+static std::map<std::string, BatchChoice> &batch_tune_cache() {
+    static std::map<std::string, BatchChoice> m;
+    return m;
+}
+
+static int batch_tune(stencil_plan *const *plans, int n, const void *const *d_in, void *const *d_out,
+                      const int64_t *T, int flags, hipStream_t st, BatchChoice *best) {
+    const std::string sig = batch_signature(plans, n, T);
+    {
+        auto it = batch_tune_cache().find(sig);
+        if (it != batch_tune_cache().end()) {
+            *best = it->second;
+            return STENCIL_OK;
+        }
+    }
+    // stencil classes whose depth the search may move
+    bool present[2][2] = {{false, false}, {false, false}};
+    for (int i = 0; i < n; ++i) {
+        const stencil_plan *p = plans[i];
+        if (p->opts.method == STENCIL_METHOD_GENERIC || p->opts.method == STENCIL_METHOD_PLAIN) continue;
+        if (p->opts.fused_k > 0 || T[i] == 0) continue;
+        present[p->r - 1][p->kind == STENCIL_BOX ? 1 : 0] = true;
+    }
+    BatchChoice cur{{{kBatchMaxK1, kBatchMaxK1}, {kBatchMaxK2, kBatchMaxK2}}, kBatchChunk};
+    float cur_ms = 0.f;
+    auto eval = [&](const BatchChoice &c, float *ms) {
+        stencil_batch *b = nullptr;
+        int rc = batch_build(&b, plans, n, d_in, d_out, T, flags & 1, st, c);
+        if (rc == STENCIL_OK) rc = time_batch(b, st, ms);
+        if (b) {
+            (void)hipStreamSynchronize(st);
+            stencil_batch_destroy(b);
+        }
+        return rc;
+    };
+    int rc = eval(cur, &cur_ms);
+    if (rc != STENCIL_OK) return rc;
+    static const int kDepths1[] = {6, 8, 10, 12};
+    static const int kDepths2[] = {2, 3, 4};
+    for (int r = 0; r < 2; ++r)
+        for (int box = 0; box < 2; ++box) {
+            if (!present[r][box]) continue;
+            const int *cand = r == 0 ? kDepths1 : kDepths2;
+            const int nc = r == 0 ? 4 : 3;
+            for (int j = 0; j < nc; ++j) {
+                if (cand[j] == cur.depth[r][box]) continue;
+                BatchChoice c = cur;
+                c.depth[r][box] = cand[j];
+                float ms = 0.f;
+                rc = eval(c, &ms);
+                if (rc != STENCIL_OK) return rc;
+                if (ms < 0.99f * cur_ms) {
+                    cur = c;
+                    cur_ms = ms;
+                }
+            }
+        }
+    static const int kRows[] = {64, 96, 128, 192, 256};
+    for (int rows : kRows) {
+        if (rows == cur.chunk) continue;
+        BatchChoice c = cur;
+        c.chunk = rows;
+        float ms = 0.f;
+        rc = eval(c, &ms);
+        if (rc != STENCIL_OK) return rc;
+        if (ms < 0.99f * cur_ms) {
+            cur = c;
+            cur_ms = ms;
+        }
+    }
+    batch_tune_cache()[sig] = cur;
+    *best = cur;
+    return STENCIL_OK;
+}
+
 }  // namespace stn
 
 using namespace stn;
@@ -268,7 +429,26 @@ extern "C" {
 int stencil_batch_create(stencil_batch **out, stencil_plan *const *plans, int n, const void *const *d_in,
                          void *const *d_out, const int64_t *T, int flags, void *stream) {
     clear_error();
-    return batch_build(out, plans, n, d_in, d_out, T, flags, (hipStream_t)stream);
+    if (!out) return fail(STENCIL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (flags & ~3) return fail(STENCIL_E_INVALID, "unknown batch flags 0x%x", flags);
+    BatchChoice ch{{{0, 0}, {0, 0}}, 0};
+    if (flags & 2) {
+        int rc = batch_validate(plans, n, d_in, d_out, T);
+        if (rc != STENCIL_OK) return rc;
+        rc = batch_tune(plans, n, d_in, d_out, T, flags, (hipStream_t)stream, &ch);
+        if (rc != STENCIL_OK) return rc;
+    }
+    return batch_build(out, plans, n, d_in, d_out, T, flags & 1, (hipStream_t)stream, ch);
+}
+
+int stencil_batch_choice(const stencil_batch *b, int *depths, int *chunk) {
+    clear_error();
+    if (!b) return fail(STENCIL_E_INVALID, "batch is NULL");
+    if (depths)
+        for (int i = 0; i < 4; ++i) depths[i] = b->depth[i / 2][i % 2];
+    if (chunk) *chunk = b->chunk;
+    return STENCIL_OK;
 }
 
 int stencil_batch_launch(stencil_batch *b, void *stream) {
@@ -323,7 +503,7 @@ int stencil_run_batched(stencil_plan *const *plans, int n, const void *const *d_
                         const int64_t *T, void *stream) {
     clear_error();
     stencil_batch *b = nullptr;
-    int rc = batch_build(&b, plans, n, d_in, d_out, T, 0, (hipStream_t)stream);
+    int rc = batch_build(&b, plans, n, d_in, d_out, T, 0, (hipStream_t)stream, BatchChoice{{{0, 0}, {0, 0}}, 0});
     if (rc != STENCIL_OK) return rc;
     rc = stencil_batch_launch(b, stream);
     // the batch owns device memory the launch uses: wait before freeing it

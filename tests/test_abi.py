@@ -151,6 +151,17 @@ def test_batched_rejects_bad_plans_before_any_device_call(L):
     assert create([h2, hd], [16, 48], [32, 64]) == _lib.STENCIL_E_INVALID  # mixed dtypes
     assert create([h2], [None], [32]) == _lib.STENCIL_E_INVALID
     assert out.value is None
+
+    def create_flags(plans, ins, outs, flags):
+        n = len(plans)
+        return L.stencil_batch_create(ctypes.byref(out), (P * n)(*plans), n, (P * n)(*ins), (P * n)(*outs),
+                                      one, flags, None)
+    # unknown flag bits, and the item tuner (bit 1) rejects bad batches before it times anything
+    assert create_flags([h2], [16], [32], 4) == _lib.STENCIL_E_INVALID
+    assert create_flags([h2], [16], [16], 2) == _lib.STENCIL_E_INVALID
+    assert create_flags([h3], [16], [32], 2) == _lib.STENCIL_E_UNSUPPORTED
+    assert out.value is None
+    assert L.stencil_batch_choice(None, None, None) == _lib.STENCIL_E_INVALID
     assert L.stencil_batch_launch(None, None) == _lib.STENCIL_E_INVALID
     assert L.stencil_batch_set_wait_limit(None, 10, None) == _lib.STENCIL_E_INVALID
     L.stencil_batch_destroy(None)

@@ -112,6 +112,34 @@ def test_batch_with_autotune_flag():
     b.close()
 
 
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_item_tuner_keeps_every_grid_equal_to_its_single_run(dt):
+    """Flags bit 1: the depth and rows chosen by timing the batch's own replays
+    change only the work split (FP32 and FP64 fused passes are bitwise equal to
+    one-step sweeps), the choice lies in the searched sets, and a second batch of
+    the same workload takes the cached choice."""
+    specs, plans, xs = _mixed_batch(7, 14, dt=dt)
+    Ts = [s[4] for s in specs]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    say("item tuner %s: tuning" % dt)
+    b = Batch(plans, xs, ys, Ts, tune_items=True)
+    depths, chunk = b.choice()
+    say("item tuner %s: depths %s, rows %d" % (dt, depths, chunk))
+    assert depths[0] in (0, 6, 8, 10, 12) and depths[1] in (0, 6, 8, 10, 12)
+    assert depths[2] in (0, 2, 3, 4) and depths[3] in (0, 2, 3, 4)
+    assert chunk in (64, 96, 128, 192, 256)
+    for y in ys:
+        y.fill_(float("nan"))
+    b.launch()
+    b.status()
+    for i, (p, x, y, T) in enumerate(zip(plans, xs, ys, Ts)):
+        assert torch.equal(y, p.run(x, T)), i
+    b2 = Batch(plans, xs, ys, Ts, tune_items=True)
+    assert b2.choice() == (depths, chunk)
+    b2.close()
+    b.close()
+
+
 def test_batch_argument_errors():
     specs, plans, xs = _mixed_batch(5, 3)
     ys = [torch.empty_like(x) for x in xs]
@@ -157,6 +185,18 @@ def test_paper_scale_batch_equals_single_runs():
         say("  grid %d %s %s T=%d: rel err %.3e" % (i, g.shape, "box" if g.kind else "star", g.T, err))
         assert err <= 1e-5, (i, err)
     b.close()
+    # the item tuner on the same workload: every grid bitwise equal to the default batch's
+    ys2 = [torch.full_like(x, float("nan")) for x in xs]
+    say("paper-scale batch: tuning the items")
+    bt = Batch(plans, xs, ys2, Ts, tune_items=True)
+    say("  tuned depths %s, rows %d" % bt.choice())
+    for y in ys2:
+        y.fill_(float("nan"))
+    bt.launch()
+    bt.status()
+    for i, (y, y2) in enumerate(zip(ys, ys2)):
+        assert torch.equal(y, y2), i
+    bt.close()
 
 
 def test_wait_limit_gives_up_and_the_next_replay_recovers():
