@@ -20,6 +20,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -345,8 +346,13 @@ static std::string batch_signature(stencil_plan *const *plans, int n, const int6
     return sig;
 }
 
+// guarded by batch_tune_mutex() (batches may be created from several threads)
 static std::map<std::string, BatchChoice> &batch_tune_cache() {
     static std::map<std::string, BatchChoice> m;
+    return m;
+}
+static std::mutex &batch_tune_mutex() {
+    static std::mutex m;
     return m;
 }
 
@@ -354,6 +360,7 @@ static int batch_tune(stencil_plan *const *plans, int n, const void *const *d_in
                       const int64_t *T, int flags, hipStream_t st, BatchChoice *best) {
     const std::string sig = batch_signature(plans, n, T);
     {
+        std::lock_guard<std::mutex> g(batch_tune_mutex());
         auto it = batch_tune_cache().find(sig);
         if (it != batch_tune_cache().end()) {
             *best = it->second;
@@ -415,7 +422,10 @@ static int batch_tune(stencil_plan *const *plans, int n, const void *const *d_in
             cur_ms = ms;
         }
     }
-    batch_tune_cache()[sig] = cur;
+    {
+        std::lock_guard<std::mutex> g(batch_tune_mutex());
+        batch_tune_cache()[sig] = cur;
+    }
     *best = cur;
     return STENCIL_OK;
 }
