@@ -257,8 +257,11 @@ int stencil_batch_set_wait_limit(stencil_batch *b, int64_t limit_us, void *strea
  * (ceil(T/ckpt) + ckpt + 2) fields, or + 2 ckpt where the fused adjoint pass
  * applies: it rebuilds the next segment on a second stream owned by the plan
  * while the current one runs, and `stream` waits for that stream before the
- * call's work ends).  One call at a time per plan.  F64 and F32 plans only
- * (STENCIL_E_UNSUPPORTED otherwise). */
+ * call's work ends).  The workspace comes stream-ordered from a memory pool
+ * the library keeps per device, which holds freed blocks for later calls
+ * instead of returning them to the system (its reserve only grows, up to the
+ * largest workspace used at once).  One call at a time per plan.  F64 and F32
+ * plans only (STENCIL_E_UNSUPPORTED otherwise). */
 int stencil_adjoint(stencil_plan *p, const void *d_u0, const void *d_gT, int64_t T,
                     int64_t checkpoint_every, void *d_grad_u0, double *d_grad_coeffs,
                     void *stream);
@@ -271,7 +274,9 @@ int stencil_adjoint(stencil_plan *p, const void *d_u0, const void *d_gT, int64_t
  *   [0] sum u   [1] sum u^2   [2] max |u|
  *   [3] sum (u-ref)^2   [4] max |u-ref|   [5] max |ref|   (0 when d_ref is NULL)
  * The result is deterministic for a given n and pointer alignment (fixed
- * partial layout; vector loads when both pointers are 4-element aligned). */
+ * partial layout; vector loads when both pointers are 4-element aligned).
+ * Its 96 KiB of partials come stream-ordered from the library's per-device
+ * memory pool (see stencil_adjoint). */
 int stencil_reduce(int dtype, const void *d_u, const void *d_ref, int64_t n, double *d_out,
                    void *stream);
 

@@ -601,7 +601,7 @@ static int adjoint_impl(stencil_plan *p, const Exec &ex, const Exec &ex1, const 
     const size_t tab_bytes = off3m.size() * sizeof(int);
     const size_t ws_bytes = (size_t)(nck + nbuf * nst + 2) * fstride + part_bytes + tab_bytes;
     char *ws = nullptr;
-    STN_HIP(hipMallocAsync((void **)&ws, ws_bytes, st));
+    STN_HIP(workspace_alloc((void **)&ws, ws_bytes, st));
     auto ck = [&](int64_t s) -> void * { return s == 0 ? const_cast<void *>(d_u0) : ws + (size_t)(s - 1) * fstride; };
     char *seg_buf[2] = {ws + (size_t)nck * fstride, ws + (size_t)(nck + (nbuf - 1) * nst) * fstride};
     char *lam_buf[2] = {ws + (size_t)(nck + nbuf * nst) * fstride, ws + (size_t)(nck + nbuf * nst + 1) * fstride};

