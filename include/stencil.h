@@ -258,9 +258,9 @@ int stencil_batch_set_wait_limit(stencil_batch *b, int64_t limit_us, void *strea
  * applies: it rebuilds the next segment on a second stream owned by the plan
  * while the current one runs, and `stream` waits for that stream before the
  * call's work ends).  The workspace comes stream-ordered from a memory pool
- * the library keeps per device, which holds freed blocks for later calls
- * instead of returning them to the system (its reserve only grows, up to the
- * largest workspace used at once).  One call at a time per plan.  F64 and F32
+ * the library keeps per device, which holds up to 8 GiB of freed blocks for
+ * later calls instead of returning them to the system at the next
+ * synchronisation.  One call at a time per plan.  F64 and F32
  * plans only (STENCIL_E_UNSUPPORTED otherwise). */
 int stencil_adjoint(stencil_plan *p, const void *d_u0, const void *d_gT, int64_t T,
                     int64_t checkpoint_every, void *d_grad_u0, double *d_grad_coeffs,

@@ -452,11 +452,12 @@ static void tune_file_store(const std::map<std::string, Exec> &m) {
     if (!ok || rename(tmp.c_str(), path.c_str()) != 0) remove(tmp.c_str());
 }
 
-// One pool per device, created on first use with the release threshold at its
-// maximum.  The device's default pool releases its memory at every
-// synchronisation; the adjoint's workspace (about 28 fields) was then mapped
-// again on every call (256^3 FP32, T = 100: 7.6 ms per call, 7.25 ms with the
-// memory kept).
+// One pool per device, created on first use, that keeps up to kPoolKeepBytes of
+// freed blocks reserved across synchronisations (beyond that it releases them,
+// as the device's default pool releases everything).  With the default pool
+// the adjoint's workspace (about 28 fields) was mapped again on every call
+// (256^3 FP32, T = 100: 7.6 ms per call, 7.25 ms with the memory kept).
+constexpr uint64_t kPoolKeepBytes = (uint64_t)8 << 30;
 hipError_t workspace_alloc(void **ptr, size_t bytes, hipStream_t st) {
     constexpr int kMaxDevices = 64;
     static std::mutex mu;
@@ -478,7 +479,7 @@ hipError_t workspace_alloc(void **ptr, size_t bytes, hipStream_t st) {
             hipMemPool_t np = nullptr;
             e = hipMemPoolCreate(&np, &props);
             if (e != hipSuccess) return e;
-            uint64_t keep = UINT64_MAX;
+            uint64_t keep = kPoolKeepBytes;
             e = hipMemPoolSetAttribute(np, hipMemPoolAttrReleaseThreshold, &keep);
             if (e != hipSuccess) {
                 (void)hipMemPoolDestroy(np);

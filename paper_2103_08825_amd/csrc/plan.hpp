@@ -90,8 +90,8 @@ hipError_t launch_reduce(int dtype, const void *u, const void *ref, int64_t n, d
                          double *out, hipStream_t st);
 int reduce_partials_bytes();
 // Stream-ordered workspace from the library's memory pool on the current
-// device: freed blocks stay reserved for later calls (the pool never returns
-// memory to the system), so repeated calls do not map and unmap it each time.
-// Free with hipFreeAsync.
+// device: up to 8 GiB of freed blocks stay reserved for later calls, so
+// repeated calls do not map and unmap their workspace each time.  Free with
+// hipFreeAsync.
 hipError_t workspace_alloc(void **ptr, size_t bytes, hipStream_t st);
 }  // namespace stn
